@@ -1,0 +1,129 @@
+/*
+ * osbf.h -- C ABI of the MI355X (gfx950) one-sided box filter.
+ *
+ * The filter is Alg. 2 of Gong, "One-Sided Box Filter for Edge Preserving
+ * Image Smoothing" (arXiv 2108.05021), Sec. III-A: for every pixel take the
+ * means of the eight one-sided windows of Eq. 6-13 (four (r+1)x(r+1)
+ * quadrants and four (r+1)x(2r+1) halves, all containing the pixel), replace
+ * the pixel by the mean closest to its current value, and repeat.
+ *
+ * Conventions shared by every entry point
+ *   - A plane is H rows by W columns, row-major and contiguous; x is the
+ *     column (rightwards), y the row (downwards).  Channels and batch images
+ *     are independent planes (the paper filters colour channels separately,
+ *     Sec. IV), laid out back to back: element (p, y, x) is at p*H*W + y*W + x.
+ *   - Windows, with y pointing down: R = [x, x+r] x [y-r, y+r],
+ *     L = [x-r, x] x [y-r, y+r], D = [x-r, x+r] x [y, y+r],
+ *     U = [x-r, x+r] x [y-r, y], SE = [x, x+r] x [y, y+r],
+ *     SW = [x-r, x] x [y, y+r], NE = [x, x+r] x [y-r, y],
+ *     NW = [x-r, x] x [y-r, y].  (The paper's N1..N8 are SW, SE, NE, NW,
+ *     L, R, D, U.)  osbf_window numbers them in this order, which is also
+ *     the tie order: among windows at the same distance the lowest number
+ *     wins.
+ *   - Distance: the selection minimises |w_i S_i - N c| over the window sums
+ *     S_i, with c the pixel's value, N = (r+1)^2 (2r+1), w_i = 2r+1 for
+ *     quadrants and r+1 for halves -- N times the |mean_i - c| of Alg. 2.
+ *     Arithmetic is FP32 whatever the storage type, so on integer-valued
+ *     images with N * max|value| < 2^24 every comparison is exact.
+ *   - Boundary: OSBF_BOUNDARY_REPLICATE reads the replicate extension of the
+ *     current iterate at every sweep, U(clamp(x), clamp(y)).
+ *   - Iteration: exactly T Jacobi sweeps (sweep t+1 reads sweep t only).
+ *     T = 0 or r = 0 is an identity copy.
+ *   - Device pointers are plain HIP device (or managed) pointers; `stream`
+ *     is a hipStream_t (NULL = the null stream).  Every call is asynchronous
+ *     and stream-ordered; the library never allocates, frees or retains
+ *     caller memory, and keeps no state beyond a read-only table of tuned
+ *     launch shapes.
+ *   - Arguments are validated on the host before anything is enqueued; on
+ *     error nothing is enqueued and the status says why (see
+ *     osbf_last_error() for a message).  Inputs must be finite: NaN or Inf
+ *     make the selection unspecified (no fault).
+ */
+#ifndef OSBF_H
+#define OSBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OSBF_ABI_VERSION 1
+#define OSBF_MAX_RADIUS 32          /* largest supported r */
+
+typedef enum {
+    OSBF_SUCCESS = 0,
+    OSBF_ERROR_INVALID_VALUE = 1,   /* null pointer, bad size, out-of-range enum */
+    OSBF_ERROR_UNSUPPORTED = 2,     /* valid request this build cannot serve */
+    OSBF_ERROR_WORKSPACE = 3,       /* workspace missing or too small */
+    OSBF_ERROR_HIP = 4,             /* a HIP runtime call or launch failed */
+    OSBF_ERROR_TIMEOUT = 5          /* a device-side bounded wait expired */
+} osbf_status;
+
+typedef enum {
+    OSBF_F32 = 0,                   /* float */
+    OSBF_F16 = 1,                   /* IEEE half; iterate rounded to nearest even every sweep */
+    OSBF_BF16 = 2                   /* bfloat16; iterate rounded to nearest even every sweep */
+} osbf_dtype;
+
+typedef enum { OSBF_BOUNDARY_REPLICATE = 0 } osbf_boundary;
+
+typedef enum {
+    OSBF_WIN_R = 0, OSBF_WIN_L = 1, OSBF_WIN_D = 2, OSBF_WIN_U = 3,
+    OSBF_WIN_SE = 4, OSBF_WIN_SW = 5, OSBF_WIN_NE = 6, OSBF_WIN_NW = 7
+} osbf_window;
+
+/* ABI version (OSBF_ABI_VERSION of the built library). */
+int32_t osbf_abi_version(void);
+
+/* Static, never-NULL description of a status code. */
+const char *osbf_status_string(osbf_status s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *osbf_last_error(void);
+
+/*
+ * Workspace bytes osbf_forward needs for these sizes (Alg. 2 iterates need one
+ * extra plane set to ping-pong through).  Returns 0 when no workspace is
+ * needed (T <= 1 with src != dst is served without one) -- callers may always
+ * pass at least this many bytes.  Returns (size_t)-1 for invalid sizes.
+ */
+size_t osbf_forward_workspace_size(int32_t planes, int32_t height, int32_t width,
+                                   osbf_dtype dtype, int32_t radius, int32_t iterations);
+
+/*
+ * osbf_forward -- T sweeps of Alg. 2 on `planes` independent planes.
+ *
+ *   src, dst   device, [planes][H][W] of `dtype`; may be equal (in place).
+ *   sel        nullable device uint8 [T][planes][H][W]: the window index
+ *              (osbf_window) each pixel selected at each sweep.
+ *   ckpt       nullable device [ceil(T/ck)][planes][H][W] of `dtype`: the
+ *              iterates U^0, U^ck, U^2ck, ... (U^0 is a copy of src), for
+ *              recomputing selections in osbf_backward.
+ *   ck         checkpoint interval (>= 1) when ckpt is non-NULL, else ignored.
+ *   ws         device workspace of ws_bytes >= osbf_forward_workspace_size().
+ *
+ * The output does not depend on whether sel/ckpt are requested.
+ */
+osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t height,
+                         int32_t width, osbf_dtype dtype, int32_t radius,
+                         int32_t iterations, osbf_boundary boundary, uint8_t *sel,
+                         void *ckpt, int32_t ck, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * osbf_forward_plan -- the launch plan osbf_forward uses for these arguments
+ * (for profiling and tests; no device work).  Writes the output tile shape,
+ * the sweeps fused per launch and the number of kernel launches (per chunk
+ * of at most 65535 planes); ck as for osbf_forward (0 = no checkpoints).
+ * Returns OSBF_ERROR_UNSUPPORTED when no tiled plan fits the device's LDS.
+ */
+osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osbf_dtype dtype,
+                              int32_t radius, int32_t iterations, int32_t ck,
+                              int32_t *tile_w, int32_t *tile_h, int32_t *fused,
+                              int32_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OSBF_H */

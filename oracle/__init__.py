@@ -50,7 +50,7 @@ def _load():
     u8 = ctypes.POINTER(ctypes.c_uint8)
     i64 = ctypes.POINTER(ctypes.c_int64)
     ci = ctypes.c_int
-    lib.oracle_sweep.argtypes = [d, d, u8, d, ci, ci, ci, ci]
+    lib.oracle_sweep.argtypes = [d, d, u8, d, d, ci, ci, ci, ci]
     lib.oracle_sweep.restype = None
     lib.oracle_forward.argtypes = [d, d, u8, ci, ci, ci, ci, ci, ci]
     lib.oracle_forward.restype = ci
@@ -112,15 +112,19 @@ def forward(x, r: int, T: int, *, return_sel: bool = False, nthreads: int = 0):
     return (out, sel) if return_sel else out
 
 
-def sweep(u, r: int, *, nthreads: int = 0):
-    """One sweep on one plane: returns (next, sel [H,W] uint8, err [H,W,8])."""
+def sweep(u, r: int, *, nthreads: int = 0, return_means: bool = False):
+    """One sweep on one plane: returns (next, sel [H,W] uint8, err [H,W,8])
+    where err holds the scaled distances |w_i S_i - N c|; with ``return_means``
+    also the eight window means [H,W,8]."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     H, W = u.shape
     out = np.empty_like(u)
     sel = np.empty((H, W), np.uint8)
     err = np.empty((H, W, 8), np.float64)
-    _load().oracle_sweep(_pd(u), _pd(out), _pu8(sel), _pd(err), H, W, r, nthreads)
-    return out, sel, err
+    means = np.empty((H, W, 8), np.float64) if return_means else None
+    _load().oracle_sweep(_pd(u), _pd(out), _pu8(sel), _pd(err),
+                         None if means is None else _pd(means), H, W, r, nthreads)
+    return (out, sel, err, means) if return_means else (out, sel, err)
 
 
 def forward_padonce(x, r: int, T: int):

@@ -120,8 +120,9 @@ static int select_window(const double S[O_NWIN], double c, int r, double *e_out)
  *   out  [H][W]        next iterate (must not alias u)
  *   sel  [H][W]        nullable; selected window index 0..7
  *   err  [H][W][8]     nullable; e_i = |w_i S_i - N c| for every window
+ *   mean [H][W][8]     nullable; S_i / n_i for every window
  */
-void oracle_sweep(const double *u, double *out, uint8_t *sel, double *err,
+void oracle_sweep(const double *u, double *out, uint8_t *sel, double *err, double *mean,
                   int H, int W, int r, int nthreads)
 {
 #ifdef _OPENMP
@@ -136,6 +137,8 @@ void oracle_sweep(const double *u, double *out, uint8_t *sel, double *err,
             int m = select_window(S, u[p], r, err ? err + p * O_NWIN : NULL);
             out[p] = S[m] / window_count(m, r);
             if (sel) sel[p] = (uint8_t)m;
+            if (mean)
+                for (int i = 0; i < O_NWIN; ++i) mean[p * O_NWIN + i] = S[i] / window_count(i, r);
         }
     }
     (void)nthreads;
@@ -160,7 +163,7 @@ int oracle_forward(const double *in, double *out, uint8_t *sel,
         memcpy(a, in + (size_t)pl * n, n * sizeof(double));
         for (int t = 0; t < T; ++t) {
             uint8_t *s = sel ? sel + ((size_t)t * planes + pl) * n : NULL;
-            oracle_sweep(a, b, s, NULL, H, W, r, nthreads);
+            oracle_sweep(a, b, s, NULL, NULL, H, W, r, nthreads);
             double *tmp = a; a = b; b = tmp;
         }
         memcpy(out + (size_t)pl * n, a, n * sizeof(double));
@@ -292,7 +295,7 @@ int oracle_backward(const double *in, const double *grad_out, double *grad_in,
     for (int pl = 0; pl < planes; ++pl) {
         memcpy(a, in + (size_t)pl * n, n * sizeof(double));
         for (int t = 0; t < T; ++t) {
-            oracle_sweep(a, b, sel + (size_t)t * n, NULL, H, W, r, nthreads);
+            oracle_sweep(a, b, sel + (size_t)t * n, NULL, NULL, H, W, r, nthreads);
             if (sel_out) memcpy(sel_out + ((size_t)t * planes + pl) * n, sel + (size_t)t * n, n);
             double *tmp = a; a = b; b = tmp;
         }

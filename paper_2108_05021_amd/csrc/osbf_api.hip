@@ -1,0 +1,271 @@
+// C ABI of the one-sided box filter: argument validation, launch planning and
+// the sweep driver.  All device work is enqueued on the caller's stream.
+#include <mutex>
+#include <string>
+#include <vector>
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "../../include/osbf.h"
+#include "osbf_internal.h"
+
+using namespace osbf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+osbf_status fail(osbf_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+osbf_status fail(osbf_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+osbf_status hip_fail(hipError_t e, const char *what) {
+    return fail(OSBF_ERROR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t elem_bytes(osbf_dtype dt) { return dt == OSBF_F32 ? 4 : 2; }
+
+bool valid_dtype(int dt) { return dt == OSBF_F32 || dt == OSBF_F16 || dt == OSBF_BF16; }
+
+// Largest dynamic LDS a workgroup may use on the current device.
+size_t lds_limit() {
+    static std::mutex mu;
+    static std::vector<size_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0)
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+                v = 65536;
+        cache[dev] = (size_t)v;
+    }
+    return cache[dev];
+}
+
+struct Plan {
+    int tw = 0, th = 0;  // output tile (multiples of r); tw == 0: nothing fits
+    int k = 1;           // sweeps fused per launch
+    int pitch = 0, arr = 0;
+    size_t lds_bytes() const { return (size_t)4 * arr * sizeof(float); }
+};
+
+// LDS regions the planner considers (width x height, halo included).
+const int kRegions[][2] = {{64, 64}, {128, 64}, {64, 128}, {96, 96}, {128, 128}, {256, 64}, {64, 32}, {32, 32}, {80, 80}, {104, 96}};
+
+Plan make_plan(int RW, int RH, int r, int k) {
+    Plan p;
+    if (!fwd_tile_shape(RW, RH, r, k, &p.tw, &p.th)) return Plan{};
+    p.k = k;
+    fwd_lds_layout(p.tw, p.th, r, k, &p.pitch, &p.arr);
+    return p;
+}
+
+// Cost model per output pixel-sweep: LDS-resident work of the fused sweeps
+// (halo recomputation included), the clamped halo load, HBM traffic that
+// shrinks as 1/k, and a penalty when fewer than two workgroups fit on a CU.
+// OSBF_PLAN="region_index,k" forces a plan (tests and tuning).
+Plan choose_plan(int H, int W, int r, int T) {
+    const size_t limit = lds_limit();
+    const int kmax = T > 0 ? std::min(T, 8) : 1;
+    if (const char *env = getenv("OSBF_PLAN")) {
+        int g = -1, k = -1;
+        if (sscanf(env, "%d,%d", &g, &k) == 2 && g >= 0 && g < (int)(sizeof kRegions / sizeof kRegions[0]) && k >= 1) {
+            Plan p = make_plan(kRegions[g][0], kRegions[g][1], r, std::min(k, kmax));
+            if (p.tw && p.lds_bytes() <= limit) return p;
+        }
+    }
+    Plan best;
+    double best_cost = 1e300;
+    for (const auto &reg : kRegions) {
+        for (int k = 1; k <= kmax; ++k) {
+            Plan p = make_plan(reg[0], reg[1], r, k);
+            if (!p.tw || p.lds_bytes() > limit) break;
+            const double tw = std::min(p.tw, W), th = std::min(p.th, H);
+            double work = 0;
+            for (int j = 0; j < k; ++j) {
+                const double e = (double)(k - 1 - j) * r;
+                const double cw = std::min<double>(tw + 2 * e, W), ch = std::min<double>(th + 2 * e, H);
+                work += (cw + 2 * r) * (ch + r) * 0.4   // V
+                      + (cw + r) * (ch + r) * 0.6       // Q, H
+                      + cw * ch * 1.0;                  // selection
+            }
+            const double lw = std::min<double>(tw + 2.0 * k * r, W), lh = std::min<double>(th + 2.0 * k * r, H);
+            work += lw * lh * 0.25 + tw * th * 0.25;    // load + store
+            double cost = work / ((double)k * tw * th);
+            const double per_cu = 163840.0 / (double)p.lds_bytes();
+            if (per_cu < 2.0) cost *= 1.3;
+            cost += 0.6 / k;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = p;
+            }
+        }
+    }
+    return best;
+}
+
+struct Launch {
+    int t0, k;  // first sweep, sweeps in this launch
+};
+
+// Segments of ck sweeps (when checkpointing), each cut into launches of at
+// most k sweeps; recomputing one segment replays exactly the same launches.
+std::vector<Launch> make_launches(int T, int ck, int k) {
+    std::vector<Launch> v;
+    const int seg = ck > 0 ? ck : T;
+    for (int s0 = 0; s0 < T; s0 += seg) {
+        const int s1 = std::min(T, s0 + seg);
+        for (int t = s0; t < s1; t += k) v.push_back(Launch{t, std::min(k, s1 - t)});
+    }
+    return v;
+}
+
+osbf_status check_sizes(int32_t planes, int32_t H, int32_t W, int dtype, int32_t r, int32_t T) {
+    if (planes < 1 || H < 1 || W < 1)
+        return fail(OSBF_ERROR_INVALID_VALUE, "planes, height and width must be >= 1 (got %d, %d, %d)",
+                    planes, H, W);
+    if ((long long)H * W > (1LL << 40))
+        return fail(OSBF_ERROR_INVALID_VALUE, "plane too large");
+    if (!valid_dtype(dtype)) return fail(OSBF_ERROR_INVALID_VALUE, "unknown dtype %d", dtype);
+    if (r < 0 || r > OSBF_MAX_RADIUS)
+        return fail(OSBF_ERROR_INVALID_VALUE, "radius %d outside [0, %d]", r, OSBF_MAX_RADIUS);
+    if (T < 0) return fail(OSBF_ERROR_INVALID_VALUE, "iterations %d < 0", T);
+    return OSBF_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t osbf_abi_version(void) { return OSBF_ABI_VERSION; }
+
+const char *osbf_status_string(osbf_status s) {
+    switch (s) {
+    case OSBF_SUCCESS: return "success";
+    case OSBF_ERROR_INVALID_VALUE: return "invalid value";
+    case OSBF_ERROR_UNSUPPORTED: return "unsupported";
+    case OSBF_ERROR_WORKSPACE: return "workspace missing or too small";
+    case OSBF_ERROR_HIP: return "HIP runtime error";
+    case OSBF_ERROR_TIMEOUT: return "device wait timed out";
+    }
+    return "unknown status";
+}
+
+const char *osbf_last_error(void) { return g_last_error.c_str(); }
+
+size_t osbf_forward_workspace_size(int32_t planes, int32_t H, int32_t W, osbf_dtype dtype,
+                                   int32_t r, int32_t T) {
+    if (check_sizes(planes, H, W, dtype, r, T) != OSBF_SUCCESS) return (size_t)-1;
+    if (T == 0 || r == 0) return 0;
+    return (size_t)planes * H * W * elem_bytes(dtype);
+}
+
+osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
+                         osbf_dtype dtype, int32_t r, int32_t T, osbf_boundary boundary,
+                         uint8_t *sel, void *ckpt, int32_t ck, void *ws, size_t ws_bytes,
+                         void *stream_) {
+    g_last_error.clear();
+    osbf_status st = check_sizes(planes, H, W, dtype, r, T);
+    if (st != OSBF_SUCCESS) return st;
+    if (boundary != OSBF_BOUNDARY_REPLICATE)
+        return fail(OSBF_ERROR_INVALID_VALUE, "unknown boundary %d", (int)boundary);
+    if (!src || !dst) return fail(OSBF_ERROR_INVALID_VALUE, "src and dst must be non-NULL");
+    if (ckpt && ck < 1) return fail(OSBF_ERROR_INVALID_VALUE, "checkpoint interval %d < 1", ck);
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t plane_set = (size_t)planes * H * W;
+    const size_t bytes = plane_set * elem_bytes(dtype);
+    const int nck = (ckpt && T > 0) ? (T + ck - 1) / ck : 0;
+    hipError_t e;
+
+    if (T == 0 || r == 0) {  // identity; every window is the pixel itself when r = 0
+        if (src != dst && (e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy");
+        if (sel && T > 0 && (e = hipMemsetAsync(sel, OSBF_WIN_R, (size_t)T * plane_set, stream)) != hipSuccess)
+            return hip_fail(e, "memset sel");
+        for (int s = 0; s < nck; ++s)
+            if ((e = hipMemcpyAsync((char *)ckpt + s * bytes, src, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+                return hip_fail(e, "copy checkpoint");
+        return OSBF_SUCCESS;
+    }
+
+    const Plan plan = choose_plan(H, W, r, T);
+    if (!plan.tw)
+        return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
+    const std::vector<Launch> launches = make_launches(T, nck ? ck : 0, plan.k);
+    const int nl = (int)launches.size();
+    const bool need_ws = nl >= 2 || src == dst;
+    if (need_ws && (!ws || ws_bytes < bytes))
+        return fail(OSBF_ERROR_WORKSPACE, "workspace of %zu bytes required, got %zu", bytes, ws ? ws_bytes : 0);
+
+    const void *cur = src;
+    if (src == dst && (nl % 2) == 1) {
+        if ((e = hipMemcpyAsync(ws, src, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy to workspace");
+        cur = ws;
+    }
+    const int tiles_x = (W + plan.tw - 1) / plan.tw, tiles_y = (H + plan.th - 1) / plan.th;
+    const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)tiles_x * tiles_y)));
+    for (int i = 0; i < nl; ++i) {
+        void *out = ((nl - 1 - i) % 2 == 0) ? dst : ws;
+        if (nck && launches[i].t0 % ck == 0) {
+            const int s = launches[i].t0 / ck;
+            if ((e = hipMemcpyAsync((char *)ckpt + s * bytes, cur, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+                return hip_fail(e, "copy checkpoint");
+        }
+        for (int p0 = 0; p0 < planes; p0 += max_planes) {
+            const int np = std::min(max_planes, planes - p0);
+            const size_t off = (size_t)p0 * H * W;
+            FwdLaunch a;
+            a.src = (const char *)cur + off * elem_bytes(dtype);
+            a.dst = (char *)out + off * elem_bytes(dtype);
+            a.sel = sel ? sel + (size_t)launches[i].t0 * plane_set + off : nullptr;
+            a.sel_stride = (long long)plane_set;
+            a.planes = np;
+            a.H = H; a.W = W; a.r = r; a.k = launches[i].k;
+            a.tw = plan.tw; a.th = plan.th;
+            a.tiles_x = tiles_x; a.tiles_y = tiles_y;
+            fwd_lds_layout(plan.tw, plan.th, r, a.k, &a.pitch, &a.arr);
+            if ((e = launch_forward((int)dtype, a, stream)) != hipSuccess)
+                return hip_fail(e, "forward launch");
+        }
+        cur = out;
+    }
+    return OSBF_SUCCESS;
+}
+
+osbf_status osbf_forward_plan(int32_t planes, int32_t H, int32_t W, osbf_dtype dtype,
+                              int32_t r, int32_t T, int32_t ck, int32_t *tile_w,
+                              int32_t *tile_h, int32_t *fused, int32_t *launches) {
+    g_last_error.clear();
+    osbf_status st = check_sizes(planes, H, W, dtype, r, T);
+    if (st != OSBF_SUCCESS) return st;
+    if (!tile_w || !tile_h || !fused || !launches)
+        return fail(OSBF_ERROR_INVALID_VALUE, "output pointers must be non-NULL");
+    if (T == 0 || r == 0) {
+        *tile_w = *tile_h = *fused = *launches = 0;
+        return OSBF_SUCCESS;
+    }
+    const Plan plan = choose_plan(H, W, r, T);
+    if (!plan.tw)
+        return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
+    *tile_w = plan.tw;
+    *tile_h = plan.th;
+    *fused = plan.k;
+    *launches = (int32_t)make_launches(T, ck > 0 ? ck : 0, plan.k).size();
+    return OSBF_SUCCESS;
+}
+
+}  // extern "C"

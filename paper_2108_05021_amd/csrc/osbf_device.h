@@ -1,0 +1,85 @@
+// Device-side helpers shared by the one-sided box filter kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace osbf {
+
+// Storage types of the iterate.  Arithmetic is always FP32; the iterate is
+// rounded to the storage type (round to nearest even) after every sweep, also
+// inside a launch that fuses several sweeps, so results do not depend on how
+// sweeps are grouped into launches.
+enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+
+template <int DT> struct Storage;
+
+template <> struct Storage<DT_F32> {
+    using T = float;
+    static __device__ __forceinline__ float load(const T *p, size_t i) { return p[i]; }
+    static __device__ __forceinline__ T pack(float v) { return v; }
+    static __device__ __forceinline__ float round(float v) { return v; }
+};
+
+template <> struct Storage<DT_F16> {
+    using T = _Float16;
+    static __device__ __forceinline__ float load(const T *p, size_t i) { return (float)p[i]; }
+    static __device__ __forceinline__ T pack(float v) { return (T)v; }
+    static __device__ __forceinline__ float round(float v) { return (float)(T)v; }
+};
+
+template <> struct Storage<DT_BF16> {
+    using T = uint16_t;
+    static __device__ __forceinline__ float load(const T *p, size_t i) {
+        return __uint_as_float(((uint32_t)p[i]) << 16);
+    }
+    // Round to nearest even on the upper 16 bits (inputs are finite).
+    static __device__ __forceinline__ T pack(float v) {
+        uint32_t u = __float_as_uint(v);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return (T)(u >> 16);
+    }
+    static __device__ __forceinline__ float round(float v) {
+        return __uint_as_float(((uint32_t)pack(v)) << 16);
+    }
+};
+
+// Scaled distances e_i = |w_i S_i - N c| (N times |mean_i - c|, Alg. 2) and the
+// tie-ordered argmin.  `d` holds the signed w_i S_i - N c for the windows in the
+// order R, L, D, U, SE, SW, NE, NW.  A balanced tournament in which the left
+// (lower-numbered) entrant wins ties returns the lowest-numbered minimum.
+struct Pick {
+    float d;   // signed scaled difference of the winner
+    int idx;   // window index of the winner
+};
+
+__device__ __forceinline__ void duel(float &da, int &ia, float db, int ib) {
+    bool b_wins = fabsf(db) < fabsf(da);
+    da = b_wins ? db : da;
+    ia = b_wins ? ib : ia;
+}
+
+template <bool WANT_IDX>
+__device__ __forceinline__ Pick select8(const float d[8]) {
+    float a0 = d[0], a1 = d[2], a2 = d[4], a3 = d[6];
+    int i0 = 0, i1 = 2, i2 = 4, i3 = 6;
+    if (WANT_IDX) {
+        duel(a0, i0, d[1], 1); duel(a1, i1, d[3], 3);
+        duel(a2, i2, d[5], 5); duel(a3, i3, d[7], 7);
+        duel(a0, i0, a1, i1);  duel(a2, i2, a3, i3);
+        duel(a0, i0, a2, i2);
+        return Pick{a0, i0};
+    } else {
+        a0 = fabsf(d[1]) < fabsf(a0) ? d[1] : a0;
+        a1 = fabsf(d[3]) < fabsf(a1) ? d[3] : a1;
+        a2 = fabsf(d[5]) < fabsf(a2) ? d[5] : a2;
+        a3 = fabsf(d[7]) < fabsf(a3) ? d[7] : a3;
+        a0 = fabsf(a1) < fabsf(a0) ? a1 : a0;
+        a2 = fabsf(a3) < fabsf(a2) ? a3 : a2;
+        a0 = fabsf(a2) < fabsf(a0) ? a2 : a0;
+        return Pick{a0, 0};
+    }
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+}  // namespace osbf

@@ -1,0 +1,26 @@
+// Internal interfaces between the C ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace osbf {
+
+// One launch of the tiled forward kernel: k fused sweeps over every plane.
+struct FwdLaunch {
+    const void *src;      // [planes][H][W] storage type
+    void *dst;            // [planes][H][W] storage type, never aliases src
+    uint8_t *sel;         // nullable; map of this launch's first sweep, plane 0
+    long long sel_stride; // elements between consecutive sweeps' maps
+    int planes, H, W, r, k;
+    int tw, th;           // output tile, multiples of r
+    int tiles_x, tiles_y;
+    int pitch, arr;       // LDS row pitch and per-array size, in floats
+};
+
+// Output tile for an LDS region of at most RW x RH pixels (false if none).
+bool fwd_tile_shape(int RW, int RH, int r, int k, int *tw, int *th);
+void fwd_lds_layout(int tw, int th, int r, int k, int *pitch, int *arr);
+hipError_t launch_forward(int dtype, const FwdLaunch &a, hipStream_t s);
+
+}  // namespace osbf

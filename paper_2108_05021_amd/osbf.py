@@ -1,0 +1,125 @@
+"""Thin Python binding of the C ABI in ``include/osbf.h`` (ctypes).
+
+Argument marshalling only: every step of the filter runs in the HIP kernels of
+``libosbf.so``.  PyTorch provides device memory (the caching allocator) and the
+current stream.  If the library is missing the calls raise; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libosbf.so")
+
+SUCCESS = 0
+DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
+WINDOWS = ("R", "L", "D", "U", "SE", "SW", "NE", "NW")
+MAX_RADIUS = 32
+
+_lib = None
+
+
+class OsbfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"osbf status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load ``libosbf.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+    L.osbf_abi_version.argtypes = []
+    L.osbf_abi_version.restype = i32
+    L.osbf_status_string.argtypes = [ctypes.c_int]
+    L.osbf_status_string.restype = ctypes.c_char_p
+    L.osbf_last_error.argtypes = []
+    L.osbf_last_error.restype = ctypes.c_char_p
+    L.osbf_forward_workspace_size.argtypes = [i32, i32, i32, ctypes.c_int, i32, i32]
+    L.osbf_forward_workspace_size.restype = sz
+    L.osbf_forward.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int,
+                               vp, vp, i32, vp, sz, vp]
+    L.osbf_forward.restype = ctypes.c_int
+    L.osbf_forward_plan.argtypes = [i32, i32, i32, ctypes.c_int, i32, i32, i32] + [ctypes.POINTER(i32)] * 4
+    L.osbf_forward_plan.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != SUCCESS:
+        raise OsbfError(status, lib().osbf_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _geometry(x: torch.Tensor):
+    if x.dim() < 2:
+        raise ValueError("expected (..., H, W)")
+    if not x.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    H, W = x.shape[-2], x.shape[-1]
+    planes = x.numel() // (H * W) if H * W else 0
+    return planes, H, W
+
+
+def forward_workspace_size(planes, H, W, dtype, r, T) -> int:
+    return int(lib().osbf_forward_workspace_size(planes, H, W, DTYPES[dtype], r, T))
+
+
+def forward_plan(planes, H, W, dtype, r, T, ck: int = 0) -> dict:
+    """Launch plan of osbf_forward: tile shape, fused sweeps, launches."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().osbf_forward_plan(planes, H, W, DTYPES[dtype], r, T, ck, *[ctypes.byref(t) for t in v]))
+    return {"tile": (v[0].value, v[1].value), "fused": v[2].value, "launches": v[3].value}
+
+
+def osbf_forward(src, dst, r: int, T: int, *, sel=None, ckpt=None, ck: int = 0, ws=None):
+    """Direct call of the C entry point on preallocated tensors."""
+    planes, H, W = _geometry(src)
+    status = lib().osbf_forward(
+        _ptr(src), _ptr(dst), planes, H, W, DTYPES[src.dtype], r, T, 0,
+        _ptr(sel), _ptr(ckpt), ck, _ptr(ws), 0 if ws is None else ws.numel() * ws.element_size(),
+        _stream(src.device))
+    _check(status)
+
+
+def forward(x: torch.Tensor, r: int, T: int, *, return_sel: bool = False,
+            ckpt_every: int = 0, out: torch.Tensor | None = None):
+    """T sweeps of the one-sided box filter on a (..., H, W) device tensor.
+
+    Returns the filtered tensor (same shape and dtype); with ``return_sel``
+    also the uint8 selection maps [T, *x.shape]; with ``ckpt_every`` > 0 also
+    the checkpoints [ceil(T/ckpt_every), *x.shape] of U^0, U^ck, ...
+    """
+    planes, H, W = _geometry(x)
+    y = torch.empty_like(x) if out is None else out
+    sel = torch.empty((T, *x.shape), dtype=torch.uint8, device=x.device) if return_sel else None
+    ckpt = None
+    if ckpt_every > 0:
+        nck = (T + ckpt_every - 1) // ckpt_every
+        ckpt = torch.empty((nck, *x.shape), dtype=x.dtype, device=x.device)
+    nbytes = forward_workspace_size(planes, H, W, x.dtype, r, T)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=x.device) if nbytes else None
+    osbf_forward(x, y, r, T, sel=sel, ckpt=ckpt, ck=ckpt_every, ws=ws)
+    res = [y]
+    if return_sel:
+        res.append(sel)
+    if ckpt is not None:
+        res.append(ckpt)
+    return res[0] if len(res) == 1 else tuple(res)

@@ -1,0 +1,91 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/*.h declares, and rejects bad arguments before touching the device."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2108_05021_amd", "libosbf.so")
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(osbf_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libosbf.so is not built (run __graft_entry__.build())")
+    from paper_2108_05021_amd import osbf
+    return osbf.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "osbf_forward" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+    for n in names:
+        getattr(lib, n)  # resolvable through ctypes too
+
+
+def test_version_and_status_strings(lib):
+    assert lib.osbf_abi_version() == 1
+    for s in range(6):
+        assert lib.osbf_status_string(s)
+    assert lib.osbf_status_string(99) == b"unknown status"
+
+
+def test_workspace_size(lib):
+    from paper_2108_05021_amd import osbf
+    import torch
+    assert osbf.forward_workspace_size(3, 64, 80, torch.float32, 2, 5) == 3 * 64 * 80 * 4
+    assert osbf.forward_workspace_size(3, 64, 80, torch.bfloat16, 2, 5) == 3 * 64 * 80 * 2
+    assert osbf.forward_workspace_size(3, 64, 80, torch.float32, 0, 5) == 0
+    assert osbf.forward_workspace_size(3, 64, 80, torch.float32, 2, 0) == 0
+    bad = ctypes.c_size_t(-1).value
+    assert lib.osbf_forward_workspace_size(0, 64, 80, 0, 2, 5) == bad
+    assert lib.osbf_forward_workspace_size(1, 64, 80, 7, 2, 5) == bad
+    assert lib.osbf_forward_workspace_size(1, 64, 80, 0, 33, 5) == bad
+    assert lib.osbf_forward_workspace_size(1, 64, 80, 0, 2, -1) == bad
+
+
+@pytest.mark.parametrize("args,status", [
+    ((1, 0, 8, 0, 1, 1, 0), 1),     # H = 0
+    ((0, 8, 8, 0, 1, 1, 0), 1),     # planes = 0
+    ((1, 8, 8, 3, 1, 1, 0), 1),     # bad dtype
+    ((1, 8, 8, 0, -1, 1, 0), 1),    # r < 0
+    ((1, 8, 8, 0, 33, 1, 0), 1),    # r > max
+    ((1, 8, 8, 0, 1, -2, 0), 1),    # T < 0
+    ((1, 8, 8, 0, 1, 1, 4), 1),     # bad boundary
+])
+def test_forward_rejects_bad_arguments(lib, args, status):
+    planes, H, W, dt, r, T, b = args
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    rc = lib.osbf_forward(fake, fake, planes, H, W, dt, r, T, b, None, None, 0, None, 0, None)
+    assert rc == status
+    assert lib.osbf_last_error()
+
+
+def test_forward_rejects_null_pointers_and_bad_checkpoint(lib):
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.osbf_forward(None, fake, 1, 8, 8, 0, 1, 1, 0, None, None, 0, None, 0, None) == 1
+    assert lib.osbf_forward(fake, None, 1, 8, 8, 0, 1, 1, 0, None, None, 0, None, 0, None) == 1
+    assert lib.osbf_forward(fake, fake, 1, 8, 8, 0, 1, 1, 0, None, fake, 0, None, 0, None) == 1
+
+
+def test_gpu_code_object_targets_gfx950():
+    out = subprocess.run(["strings", LIB], capture_output=True, text=True).stdout
+    assert "gfx950" in out

@@ -1,0 +1,214 @@
+"""GPU parity of the forward path (osbf_forward) against the FP64 oracle.
+
+Sizes span several tiles with ragged tails; the full-size workloads are
+checked on sampled crops (teacher-forced single sweeps) and by properties.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_05021_amd import osbf, synth
+from tests.parity import check_sweep_planes, crop_check, replay_check_planes, tau
+
+pytestmark = pytest.mark.gpu
+
+TILES = [0, 1, 2, 3]
+
+
+class plan:
+    """Force a launch plan (tile id, fused sweeps) for the block."""
+
+    def __init__(self, tile, k):
+        self.v = f"{tile},{k}"
+
+    def __enter__(self):
+        self.old = os.environ.get("OSBF_PLAN")
+        os.environ["OSBF_PLAN"] = self.v
+
+    def __exit__(self, *a):
+        if self.old is None:
+            os.environ.pop("OSBF_PLAN", None)
+        else:
+            os.environ["OSBF_PLAN"] = self.old
+
+
+def _gpu(a, dev, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev).to(dtype)
+
+
+@pytest.mark.parametrize("shape", [(1, 150, 197), (2, 67, 300), (3, 33, 45), (1, 1, 50), (1, 50, 1), (1, 1, 1)])
+@pytest.mark.parametrize("r", [1, 2, 3, 5, 6, 10, 16, 23])
+def test_single_sweep(dev, shape, r):
+    """One sweep against the oracle; every tile shape gives the same bits
+    (window sums restart at image positions that are multiples of r)."""
+    rng = np.random.default_rng(hash((shape, r)) % 2**32)
+    img = synth.rectangles(shape[1], shape[2], 6, 0.05, rng, C=shape[0])
+    x = _gpu(img, dev)
+    ref = None
+    for tile in TILES:
+        with plan(tile, 1):
+            y, sel = osbf.forward(x, r, 1, return_sel=True)
+        if ref is None:
+            ref = (y, sel)
+            st = check_sweep_planes(img, y.cpu().numpy(), r, sel[0].cpu().numpy())
+            assert st["flips"] <= max(2, st["pixels"] // 1000)
+        else:
+            assert torch.equal(y, ref[0]) and torch.equal(sel, ref[1]), f"tile {tile} differs"
+
+
+def test_teacher_forced_single_workload(dev):
+    """256x256 rectangles, r=2, T=10: every sweep checked on the GPU's own iterate."""
+    img = synth.workload_single()
+    x = _gpu(img, dev)
+    flips = 0
+    for t in range(10):
+        y, sel = osbf.forward(x, 2, 1, return_sel=True)
+        st = check_sweep_planes(x.cpu().numpy(), y.cpu().numpy(), 2, sel[0].cpu().numpy())
+        flips += st["flips"]
+        x = y
+    assert flips <= 20
+    # end to end in the default plan: the oracle replays the GPU's selections
+    got, sels = osbf.forward(_gpu(img, dev), 2, 10, return_sel=True)
+    replay_check_planes(img, got.cpu().numpy(), sels.cpu().numpy(), 2, max_outliers=0)
+    # untethered: near-tie flips spread, so only the bulk must agree
+    want = oracle.forward(img.astype(np.float64), 2, 10)
+    err = np.abs(got.cpu().numpy() - want)
+    assert np.median(err) < 1e-6 and (err > 1e-5).mean() < 0.05
+
+
+@pytest.mark.parametrize("r", [1, 2, 4, 8, 16])
+def test_integer_selection_bit_exact(dev, r):
+    """Integer images: FP32 sums and scaled distances are exact, so the
+    selection map must equal the oracle's exact int64 selection bit for bit."""
+    rng = np.random.default_rng(100 + r)
+    img = synth.integer_image(97, 131, rng)[0]
+    # structured ties: a coarse integer pattern plus a flat block
+    img[10:40, 20:70] = 17
+    x = _gpu(img, dev)
+    for tile in TILES:
+        with plan(tile, 1):
+            y, sel = osbf.forward(x, r, 1, return_sel=True)
+        isel, sums = oracle.select_int64(img.astype(np.int64), r)
+        np.testing.assert_array_equal(sel[0].cpu().numpy(), isel)
+        n = np.where(np.arange(8) >= 4, (r + 1) ** 2, (r + 1) * (2 * r + 1))
+        want = np.take_along_axis(sums, isel[..., None].astype(np.int64), 2)[..., 0] / n[isel]
+        np.testing.assert_allclose(y.cpu().numpy(), want, rtol=0, atol=255 * 2.0 ** -21)
+
+
+@pytest.mark.parametrize("r,T,tile,k", [(1, 6, 0, 3), (2, 10, 1, 4), (2, 9, 2, 8), (3, 7, 2, 2),
+                                        (5, 4, 0, 2), (8, 3, 3, 3), (2, 5, 3, 5)])
+def test_fused_sweeps(dev, r, T, tile, k):
+    """k sweeps fused per launch give the same bits and maps as single-sweep
+    launches, and the oracle replaying the selection maps reproduces them."""
+    rng = np.random.default_rng(200 + r + T)
+    img = synth.voronoi(150, 173, 12, 0.05, rng, C=2)
+    x = _gpu(img, dev)
+    with plan(tile, k):
+        yf, self_f = osbf.forward(x, r, T, return_sel=True)
+    with plan(tile, 1):
+        y1, sel1 = osbf.forward(x, r, T, return_sel=True)
+    assert torch.equal(yf, y1) and torch.equal(self_f, sel1)
+    replay_check_planes(img, yf.cpu().numpy(), self_f.cpu().numpy(), r, max_outliers=0)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float16, 2.0 ** -11 * 1.1 + 1e-5), (torch.bfloat16, 2.0 ** -8 * 1.1 + 1e-5)])
+@pytest.mark.parametrize("k", [1, 3])
+def test_reduced_precision_single_sweep(dev, dtype, tol, k):
+    """F16/BF16 storage: one sweep from the stored iterate equals the oracle's
+    mean of the selected window up to half an ulp of the storage type."""
+    rng = np.random.default_rng(300)
+    img = synth.voronoi(120, 140, 10, 0.02, rng, C=1)
+    x = _gpu(img, dev, dtype)
+    x_np = x.float().cpu().numpy()
+    u = x
+    for t in range(3):
+        with plan(2, 1):
+            y, sel = osbf.forward(u, 4, 1, return_sel=True)
+        check_sweep_planes(u.float().cpu().numpy(), y.float().cpu().numpy(), 4, sel[0].cpu().numpy(), tol=tol)
+        u = y
+    with plan(2, k):
+        yk = osbf.forward(x, 4, 3)
+    with plan(2, 1):
+        y1 = osbf.forward(x, 4, 3)
+    assert torch.equal(yk, y1)
+    want = oracle.forward(x_np.astype(np.float64), 4, 3)
+    err = np.abs(yk.float().cpu().numpy() - want)
+    assert np.median(err) < tol
+
+
+def test_identity_cases(dev):
+    rng = np.random.default_rng(5)
+    img = synth.rectangles(40, 50, 3, 0.05, rng, C=2)
+    x = _gpu(img, dev)
+    y, sel = osbf.forward(x, 0, 3, return_sel=True)
+    assert torch.equal(y, x) and int(sel.max()) == 0 and sel.shape[0] == 3
+    y = osbf.forward(x, 3, 0)
+    assert torch.equal(y, x)
+
+
+@pytest.mark.parametrize("T,k", [(1, 1), (2, 1), (3, 1), (4, 2), (5, 2), (6, 3)])
+def test_in_place_matches_out_of_place(dev, T, k):
+    rng = np.random.default_rng(6)
+    img = synth.rectangles(70, 90, 5, 0.05, rng, C=2)
+    x = _gpu(img, dev)
+    with plan(2, k):
+        want = osbf.forward(x, 2, T)
+        z = x.clone()
+        ws = torch.empty(osbf.forward_workspace_size(2, 70, 90, torch.float32, 2, T), dtype=torch.uint8, device=dev)
+        osbf.osbf_forward(z, z, 2, T, ws=ws)
+    assert torch.equal(z, want)
+
+
+def test_checkpoints_and_determinism(dev):
+    rng = np.random.default_rng(7)
+    img = synth.voronoi(100, 120, 10, 0.05, rng, C=3)
+    x = _gpu(img, dev)
+    with plan(1, 2):
+        y, sel, ck = osbf.forward(x, 3, 10, return_sel=True, ckpt_every=4)
+        y2, sel2 = osbf.forward(x, 3, 10, return_sel=True)
+        assert torch.equal(y, y2) and torch.equal(sel, sel2)   # determinism, output independent of ckpt
+        assert ck.shape[0] == 3 and torch.equal(ck[0], x)
+        for s in (1, 2):
+            ys = osbf.forward(x, 3, 4 * s)
+            assert torch.equal(ck[s], ys)
+
+
+def test_workspace_and_argument_errors(dev):
+    x = torch.rand(1, 32, 32, device=dev)
+    y = torch.empty_like(x)
+    small = torch.empty(16, dtype=torch.uint8, device=dev)
+    with pytest.raises(osbf.OsbfError) as ei:
+        osbf.osbf_forward(x, y, 2, 20, ws=small)   # 20 sweeps need more than one launch
+    assert ei.value.status == 3
+    with pytest.raises(osbf.OsbfError) as ei:
+        osbf.osbf_forward(x, y, osbf.MAX_RADIUS + 1, 1)
+    assert ei.value.status == 1
+
+
+# ----------------------------------------------------------- full sizes
+
+@pytest.mark.parametrize("r", [2, 5, 10])
+def test_rgb_2048_sampled(dev, r):
+    """3x2048x2048 Voronoi workload: one sweep checked on sampled crops, and
+    the T=30 run (benchmark launch configuration) against per-sweep launches
+    and the maximum principle."""
+    img = synth.workload_rgb()
+    x = _gpu(img, dev)
+    y, sel = osbf.forward(x, r, 1, return_sel=True)
+    yn, sn, xn = y.cpu().numpy(), sel[0].cpu().numpy(), img
+    rng = np.random.default_rng(r)
+    for p in range(3):
+        for (y0, x0) in [(0, 0), (2048 - 48, 2048 - 48), (0, 1000), (1500, 0)] + \
+                [tuple(rng.integers(0, 2000, 2)) for _ in range(3)]:
+            crop_check(xn[p], yn[p], r, sn[p], int(y0), int(x0), 48)
+    T = 30
+    yT = osbf.forward(x, r, T)
+    for p in range(3):
+        assert float(yT[p].min()) >= float(x[p].min()) - 1e-6
+        assert float(yT[p].max()) <= float(x[p].max()) + 1e-6
+    with plan(0, 1):
+        y1 = osbf.forward(x, r, T)
+    assert torch.equal(yT, y1)
