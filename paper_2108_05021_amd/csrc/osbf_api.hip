@@ -56,62 +56,85 @@ size_t lds_limit() {
 }
 
 struct Plan {
+    int geom = GEOM_GENERIC;
     int tw = 0, th = 0;  // output tile (multiples of r); tw == 0: nothing fits
     int k = 1;           // sweeps fused per launch
     int pitch = 0, arr = 0;
     size_t lds_bytes() const { return (size_t)4 * arr * sizeof(float); }
 };
 
-// LDS regions the planner considers (width x height, halo included).
-const int kRegions[][2] = {{64, 64}, {128, 64}, {64, 128}, {96, 96}, {128, 128}, {256, 64}, {64, 32}, {32, 32}, {80, 80}, {104, 96}};
+// LDS regions (width x height, halo included) the generic kernel considers.
+const int kRegions[][2] = {{64, 64}, {128, 64}, {64, 128}, {96, 96}, {128, 128}, {256, 64},
+                           {64, 32}, {32, 32}, {80, 80}, {104, 96}};
 
-Plan make_plan(int RW, int RH, int r, int k) {
+Plan make_plan(int geom, int RW, int RH, int r, int k) {
     Plan p;
     if (!fwd_tile_shape(RW, RH, r, k, &p.tw, &p.th)) return Plan{};
+    p.geom = geom;
     p.k = k;
-    fwd_lds_layout(p.tw, p.th, r, k, &p.pitch, &p.arr);
+    if (geom == GEOM_GENERIC) {
+        fwd_lds_layout(p.tw, p.th, r, k, &p.pitch, &p.arr);
+    } else {
+        p.pitch = RW + 1;
+        p.arr = RH * p.pitch;
+    }
     return p;
 }
 
-// Cost model per output pixel-sweep: LDS-resident work of the fused sweeps
-// (halo recomputation included), the clamped halo load, HBM traffic that
-// shrinks as 1/k, and a penalty when fewer than two workgroups fit on a CU.
-// OSBF_PLAN="region_index,k" forces a plan (tests and tuning).
+// Cost per output pixel-sweep: selection work over the fused sweeps' grown
+// regions (halo recomputation), the cheaper running-sum phases and the halo
+// load, HBM traffic that shrinks as 1/k, and a penalty for low occupancy.
+double plan_cost(const Plan &p, int H, int W, int r) {
+    const double tw = std::min(p.tw, W), th = std::min(p.th, H);
+    double work = 0;
+    for (int j = 0; j < p.k; ++j) {
+        const double e = (double)(p.k - 1 - j) * r;
+        const double cw = std::min<double>(tw + 2 * e, W), ch = std::min<double>(th + 2 * e, H);
+        work += cw * ch * 1.0 + (cw + 2 * r) * (ch + r) * 0.08 + (cw + r) * (ch + r) * 0.15;
+    }
+    const double lw = std::min<double>(tw + 2.0 * p.k * r, W), lh = std::min<double>(th + 2.0 * p.k * r, H);
+    work += lw * lh * 0.05;
+    double cost = work / ((double)p.k * tw * th);
+    const int per_cu = (int)(163840 / std::max<size_t>(p.lds_bytes(), 1));
+    if (per_cu < 2) cost *= 1.6;
+    else if (per_cu < 3) cost *= 1.1;
+    if (p.geom == GEOM_GENERIC) cost *= 1.8;   // runtime-pitch addressing
+    return cost + 0.25 / p.k;
+}
+
+// OSBF_PLAN="geom,k" forces a plan (tests and tuning): geom 0 is the generic
+// kernel (region chosen by cost), 1..3 the fixed geometries.
 Plan choose_plan(int H, int W, int r, int T) {
     const size_t limit = lds_limit();
     const int kmax = T > 0 ? std::min(T, 8) : 1;
+    int force_geom = -1, force_k = -1;
     if (const char *env = getenv("OSBF_PLAN")) {
-        int g = -1, k = -1;
-        if (sscanf(env, "%d,%d", &g, &k) == 2 && g >= 0 && g < (int)(sizeof kRegions / sizeof kRegions[0]) && k >= 1) {
-            Plan p = make_plan(kRegions[g][0], kRegions[g][1], r, std::min(k, kmax));
-            if (p.tw && p.lds_bytes() <= limit) return p;
-        }
+        if (sscanf(env, "%d,%d", &force_geom, &force_k) != 2 || force_geom < 0 || force_geom > 3 || force_k < 1)
+            force_geom = force_k = -1;
+        else
+            force_k = std::min(force_k, kmax);
     }
     Plan best;
     double best_cost = 1e300;
-    for (const auto &reg : kRegions) {
+    auto consider = [&](const Plan &p) {
+        if (!p.tw || p.lds_bytes() > limit) return;
+        const double c = plan_cost(p, H, W, r);
+        if (c < best_cost) { best_cost = c; best = p; }
+    };
+    for (int k = 1; k <= kmax; ++k) {
+        if (force_k > 0 && k != force_k) continue;
+        if (fixed_radius(r))
+            for (int g = 1; g <= 3; ++g)
+                if (force_geom < 0 || force_geom == g)
+                    consider(make_plan(g, kGeomDims[g][0], kGeomDims[g][1], r, k));
+        if (force_geom <= 0)
+            for (const auto &reg : kRegions) consider(make_plan(GEOM_GENERIC, reg[0], reg[1], r, k));
+    }
+    if (!best.tw && force_geom >= 0) {   // forced plan does not fit: fall back to the model
         for (int k = 1; k <= kmax; ++k) {
-            Plan p = make_plan(reg[0], reg[1], r, k);
-            if (!p.tw || p.lds_bytes() > limit) break;
-            const double tw = std::min(p.tw, W), th = std::min(p.th, H);
-            double work = 0;
-            for (int j = 0; j < k; ++j) {
-                const double e = (double)(k - 1 - j) * r;
-                const double cw = std::min<double>(tw + 2 * e, W), ch = std::min<double>(th + 2 * e, H);
-                work += (cw + 2 * r) * (ch + r) * 0.4   // V
-                      + (cw + r) * (ch + r) * 0.6       // Q, H
-                      + cw * ch * 1.0;                  // selection
-            }
-            const double lw = std::min<double>(tw + 2.0 * k * r, W), lh = std::min<double>(th + 2.0 * k * r, H);
-            work += lw * lh * 0.25 + tw * th * 0.25;    // load + store
-            double cost = work / ((double)k * tw * th);
-            const double per_cu = 163840.0 / (double)p.lds_bytes();
-            if (per_cu < 2.0) cost *= 1.3;
-            cost += 0.6 / k;
-            if (cost < best_cost) {
-                best_cost = cost;
-                best = p;
-            }
+            if (fixed_radius(r))
+                for (int g = 1; g <= 3; ++g) consider(make_plan(g, kGeomDims[g][0], kGeomDims[g][1], r, k));
+            for (const auto &reg : kRegions) consider(make_plan(GEOM_GENERIC, reg[0], reg[1], r, k));
         }
     }
     return best;
@@ -237,7 +260,11 @@ osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t H, 
             a.H = H; a.W = W; a.r = r; a.k = launches[i].k;
             a.tw = plan.tw; a.th = plan.th;
             a.tiles_x = tiles_x; a.tiles_y = tiles_y;
-            fwd_lds_layout(plan.tw, plan.th, r, a.k, &a.pitch, &a.arr);
+            a.geom = plan.geom;
+            if (plan.geom == GEOM_GENERIC)
+                fwd_lds_layout(plan.tw, plan.th, r, a.k, &a.pitch, &a.arr);
+            else
+                a.pitch = plan.pitch, a.arr = plan.arr;
             if ((e = launch_forward((int)dtype, a, stream)) != hipSuccess)
                 return hip_fail(e, "forward launch");
         }

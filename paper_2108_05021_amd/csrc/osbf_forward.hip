@@ -51,10 +51,10 @@ __device__ __forceinline__ void phase_v(const float *Pi, float *Vi, int pitch, i
         for (int x = vx0 + tx; x < vx1; x += 64) {
             const float *pc = Pi + x;
             float *vc = Vi + x;
-            float v = 0.f;
+            float v = pc[cidx<CL>(y0 - r, H - 1) * pitch];
             if (R > 0) {
 #pragma unroll
-                for (int t = 0; t <= R; ++t) v += pc[cidx<CL>(y0 - R + t, H - 1) * pitch];
+                for (int t = 1; t <= R; ++t) v += pc[cidx<CL>(y0 - R + t, H - 1) * pitch];
                 vc[y0 * pitch] = v;
 #pragma unroll
                 for (int t = 1; t < R; ++t) {
@@ -65,7 +65,7 @@ __device__ __forceinline__ void phase_v(const float *Pi, float *Vi, int pitch, i
                     }
                 }
             } else {
-                for (int t = 0; t <= r; ++t) v += pc[cidx<CL>(y0 - r + t, H - 1) * pitch];
+                for (int t = 1; t <= r; ++t) v += pc[cidx<CL>(y0 - r + t, H - 1) * pitch];
                 vc[y0 * pitch] = v;
                 for (int y = y0 + 1; y < y1; ++y) {
                     v += pc[cidx<CL>(y, H - 1) * pitch] - pc[cidx<CL>(y - r - 1, H - 1) * pitch];
@@ -94,10 +94,11 @@ __device__ __forceinline__ void phase_qh(const float *Pi, const float *Vi, float
             const float *pr = Pi + y * pitch;
             float *qr = Qi + y * pitch;
             float *hr = Hi + y * pitch;
-            float q = 0.f, h = 0.f;
+            const int c0 = cidx<CL>(x0 - r, W - 1);
+            float q = vr[c0], h = doH ? pr[c0] : 0.f;
             if (R > 0) {
 #pragma unroll
-                for (int t = 0; t <= R; ++t) {
+                for (int t = 1; t <= R; ++t) {
                     const int cx = cidx<CL>(x0 - R + t, W - 1);
                     q += vr[cx];
                     if (doH) h += pr[cx];
@@ -118,7 +119,7 @@ __device__ __forceinline__ void phase_qh(const float *Pi, const float *Vi, float
                     }
                 }
             } else {
-                for (int t = 0; t <= r; ++t) {
+                for (int t = 1; t <= r; ++t) {
                     const int cx = cidx<CL>(x0 - r + t, W - 1);
                     q += vr[cx];
                     if (doH) h += pr[cx];
@@ -254,8 +255,230 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(FwdLaunch a) {
     fwd_tile<DT, R, SEL>(a, tile % a.tiles_x, tile / a.tiles_x, plane, lds);
 }
 
+// Phase A of the fixed-geometry kernel: V on columns [max(0,xa-R),
+// min(W,xb+R)), rows [ya, yb+R), in blocks of R rows anchored at multiples of
+// R.  Each lane owns one region column; a block's 2R input rows are read once.
+template <int R, int RW, int RH, bool CL>
+__device__ __forceinline__ void fixed_phase_v(const float *P, float *V, int lx, int ly, int ox,
+                                              int oy, int H, int W, int xa, int xb, int ya, int yb) {
+    constexpr int PITCH = RW + 1;
+    constexpr int NY = 256 / RW;
+    const int x = ox + lx;
+    if (x < max(0, xa - R) || x >= min(W, xb + R)) return;
+    const int yend = yb + R;
+    const int nblk = (yend - ya + R - 1) / R;
+    for (int b = ly; b < nblk; b += NY) {
+        const int y0 = ya + b * R;
+        float p[2 * R];
+        if (!CL) {
+            const float *pc = P + (y0 - R - oy) * PITCH + lx;
+#pragma unroll
+            for (int t = 0; t < 2 * R; ++t) p[t] = pc[t * PITCH];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 2 * R; ++t) p[t] = P[(min(max(y0 - R + t, 0), H - 1) - oy) * PITCH + lx];
+        }
+        float *vc = V + (y0 - oy) * PITCH + lx;
+        float v = p[0];
+#pragma unroll
+        for (int t = 1; t <= R; ++t) v += p[t];
+        vc[0] = v;
+        if (y0 + R <= yend) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                v += p[R + t] - p[t - 1];
+                vc[t * PITCH] = v;
+            }
+        } else {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                if (y0 + t < yend) {
+                    v += p[R + t] - p[t - 1];
+                    vc[t * PITCH] = v;
+                }
+            }
+        }
+    }
+}
+
+// Phase B of the fixed-geometry kernel: Q on columns [xa, xb+R), rows
+// [ya, yb+R); H on the same columns, rows [ya, yb).  One lane per region row.
+template <int R, int RW, int RH, bool CL>
+__device__ __forceinline__ void fixed_phase_qh(const float *P, const float *V, float *Q, float *Hs,
+                                               int lr, int lb, int ox, int oy, int W, int xa,
+                                               int xb, int ya, int yb) {
+    constexpr int PITCH = RW + 1;
+    const int y = oy + lr;
+    if (lr >= RH || y < ya || y >= yb + R) return;
+    const bool doH = y < yb;
+    const int xend = xb + R;
+    const int nblk = (xend - xa + R - 1) / R;
+    for (int b = lb; b < nblk; b += 4) {
+        const int x0 = xa + b * R;
+        float v[2 * R], p[2 * R];
+        if (!CL) {
+            const int o = lr * PITCH + (x0 - R - ox);
+#pragma unroll
+            for (int t = 0; t < 2 * R; ++t) {
+                v[t] = V[o + t];
+                p[t] = P[o + t];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 2 * R; ++t) {
+                const int o = lr * PITCH + (min(max(x0 - R + t, 0), W - 1) - ox);
+                v[t] = V[o];
+                p[t] = P[o];
+            }
+        }
+        float *qr = Q + lr * PITCH + (x0 - ox);
+        float *hr = Hs + lr * PITCH + (x0 - ox);
+        float q = v[0], h = p[0];
+#pragma unroll
+        for (int t = 1; t <= R; ++t) {
+            q += v[t];
+            h += p[t];
+        }
+        qr[0] = q;
+        if (doH) hr[0] = h;
+        if (x0 + R <= xend) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                q += v[R + t] - v[t - 1];
+                h += p[R + t] - p[t - 1];
+                qr[t] = q;
+                if (doH) hr[t] = h;
+            }
+        } else {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                if (x0 + t < xend) {
+                    q += v[R + t] - v[t - 1];
+                    h += p[R + t] - p[t - 1];
+                    qr[t] = q;
+                    if (doH) hr[t] = h;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-geometry kernel for the common radii.  The LDS region is RW x RH
+// pixels (halo included) with a compile-time pitch, so every LDS access is an
+// immediate offset from one base address; one wave spans a region row.  The
+// arithmetic is the same sequence of FP32 operations as fwd_tile (same block
+// anchors, same summation order), so both kernels give identical bits.
+template <int DT, int R, int RW, int RH, bool SEL>
+__device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int tile_y, int plane,
+                                          float *lds) {
+    using S = Storage<DT>;
+    constexpr int PITCH = RW + 1;
+    constexpr int ARR = RH * PITCH;
+    constexpr int NY = 256 / RW;  // waves stacked vertically
+    static_assert(RW == 64 || RW == 128, "region width");
+    static_assert(RH <= 64, "phase B maps one lane per region row");
+    float *const P = lds;
+    float *const V = lds + ARR;
+    float *const Q = lds + 2 * ARR;
+    float *const Hs = lds + 3 * ARR;
+    const int tid = threadIdx.x;
+    // phase A / C: lane = region column; phase B: lane = region row.  The
+    // wave-level indices are uniform, so loop control stays on the SALU.
+    const int lx = tid % RW, ly = __builtin_amdgcn_readfirstlane(tid / RW);
+    const int lr = tid & 63, lb = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int H = a.H, W = a.W, k = a.k, TW = a.tw, TH = a.th;
+    const int ext = k * R;
+    const int X0 = tile_x * TW, Y0 = tile_y * TH;
+    const int ox = X0 - ext, oy = Y0 - ext;  // image coords of LDS (0,0)
+    const size_t plane_off = (size_t)plane * H * W;
+    const typename S::T *src = (const typename S::T *)a.src + plane_off;
+    const bool interior = (X0 - ext >= 0) && (Y0 - ext >= 0) && (X0 + TW + ext <= W) &&
+                          (Y0 + TH + ext <= H);
+
+    {   // clamped load of tile + halo
+        const int x = ox + lx;
+        const int y0 = max(0, oy), y1 = min(H, Y0 + TH + ext);
+        if (x >= 0 && x < W && lx < TW + 2 * ext) {
+            for (int y = y0 + ly; y < y1; y += NY)
+                P[(y - oy) * PITCH + lx] = S::load(src, (size_t)y * W + x);
+        }
+    }
+    __syncthreads();
+
+    constexpr float fr1 = (float)(R + 1), f2r1 = (float)(2 * R + 1);
+    constexpr float N = fr1 * fr1 * f2r1;
+    const float invN = 1.0f / N;
+
+    for (int j = 0; j < k; ++j) {
+        const int e = (k - 1 - j) * R;
+        const int xa = max(0, X0 - e), xb = min(W, X0 + TW + e);
+        const int ya = max(0, Y0 - e), yb = min(H, Y0 + TH + e);
+
+        if (interior) {
+            fixed_phase_v<R, RW, RH, false>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
+            __syncthreads();
+            fixed_phase_qh<R, RW, RH, false>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
+        } else {
+            fixed_phase_v<R, RW, RH, true>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
+            __syncthreads();
+            fixed_phase_qh<R, RW, RH, true>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
+        }
+        __syncthreads();
+
+        // Phase C: selection and update on [xa, xb) x [ya, yb).
+        {
+            const bool last = (j == k - 1);
+            const int x = ox + lx;
+            if (x >= xa && x < xb) {
+                uint8_t *sel = SEL ? a.sel + (size_t)j * a.sel_stride + plane_off : nullptr;
+                typename S::T *dst = (typename S::T *)a.dst + plane_off;
+                const bool core_x = x >= X0 && x < X0 + TW;
+                for (int y = ya + ly; y < yb; y += NY) {
+                    const int o = (y - oy) * PITCH + lx;
+                    constexpr int RD = R * PITCH;
+                    const float c = P[o];
+                    const float nw = Q[o], ne = Q[o + R], sw = Q[o + RD], se = Q[o + RD + R];
+                    const float sR = ne + se - Hs[o + R];
+                    const float sL = nw + sw - Hs[o];
+                    const float sD = sw + se - V[o + RD];
+                    const float sU = nw + ne - V[o];
+                    const float nc = -N * c;
+                    float d[8];
+                    d[0] = fmaf(fr1, sR, nc);
+                    d[1] = fmaf(fr1, sL, nc);
+                    d[2] = fmaf(fr1, sD, nc);
+                    d[3] = fmaf(fr1, sU, nc);
+                    d[4] = fmaf(f2r1, se, nc);
+                    d[5] = fmaf(f2r1, sw, nc);
+                    d[6] = fmaf(f2r1, ne, nc);
+                    d[7] = fmaf(f2r1, nw, nc);
+                    const Pick pk = select8<SEL>(d);
+                    const float u = S::round(fmaf(pk.d, invN, c));
+                    if (SEL && core_x && y >= Y0 && y < Y0 + TH) sel[(size_t)y * W + x] = (uint8_t)pk.idx;
+                    if (last)
+                        dst[(size_t)y * W + x] = S::pack(u);
+                    else
+                        P[o] = u;
+                }
+            }
+            if (!last) __syncthreads();
+        }
+    }
+}
+
+template <int DT, int R, int RW, int RH, bool SEL>
+__global__ __launch_bounds__(256) void fwd_fixed_kernel(FwdLaunch a) {
+    extern __shared__ float lds[];
+    const int ntiles = a.tiles_x * a.tiles_y;
+    const int total = ntiles * a.planes;
+    const int t = xcd_remap(blockIdx.x, total);
+    const int plane = t / ntiles, tile = t - plane * ntiles;
+    fwd_fixed<DT, R, RW, RH, SEL>(a, tile % a.tiles_x, tile / a.tiles_x, plane, lds);
+}
+
 template <int DT, int R, bool SEL>
-static hipError_t launch_fwd(const FwdLaunch &a, hipStream_t stream) {
+[[maybe_unused]] static hipError_t launch_fwd(const FwdLaunch &a, hipStream_t stream) {
     const size_t lds = (size_t)4 * a.arr * sizeof(float);
     auto kern = fwd_tile_kernel<DT, R, SEL>;
     if (lds > 65536) {
@@ -268,19 +491,50 @@ static hipError_t launch_fwd(const FwdLaunch &a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int DT, int R, int RW, int RH, bool SEL>
+static hipError_t launch_fixed(const FwdLaunch &a, hipStream_t stream) {
+    const size_t lds = (size_t)4 * RH * (RW + 1) * sizeof(float);
+    auto kern = fwd_fixed_kernel<DT, R, RW, RH, SEL>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int blocks = a.tiles_x * a.tiles_y * a.planes;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, stream, a);
+    return hipGetLastError();
+}
+
+template <int DT, int R, bool SEL>
+static hipError_t launch_fixed_geom(const FwdLaunch &a, hipStream_t s) {
+    switch (a.geom) {
+    case GEOM_64x60: return launch_fixed<DT, R, 64, 60, SEL>(a, s);
+    case GEOM_64x48: return launch_fixed<DT, R, 64, 48, SEL>(a, s);
+    case GEOM_128x32: return launch_fixed<DT, R, 128, 32, SEL>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int DT, bool SEL>
 static hipError_t launch_fwd_r(const FwdLaunch &a, hipStream_t s) {
+    if (a.geom == GEOM_GENERIC) return launch_fwd<DT, 0, SEL>(a, s);
     switch (a.r) {
-    case 1: return launch_fwd<DT, 1, SEL>(a, s);
-    case 2: return launch_fwd<DT, 2, SEL>(a, s);
-    case 3: return launch_fwd<DT, 3, SEL>(a, s);
-    case 4: return launch_fwd<DT, 4, SEL>(a, s);
-    case 5: return launch_fwd<DT, 5, SEL>(a, s);
-    case 8: return launch_fwd<DT, 8, SEL>(a, s);
-    case 10: return launch_fwd<DT, 10, SEL>(a, s);
-    case 16: return launch_fwd<DT, 16, SEL>(a, s);
-    default: return launch_fwd<DT, 0, SEL>(a, s);
+    case 1: return launch_fixed_geom<DT, 1, SEL>(a, s);
+    case 2: return launch_fixed_geom<DT, 2, SEL>(a, s);
+    case 3: return launch_fixed_geom<DT, 3, SEL>(a, s);
+    case 4: return launch_fixed_geom<DT, 4, SEL>(a, s);
+    case 5: return launch_fixed_geom<DT, 5, SEL>(a, s);
+    case 8: return launch_fixed_geom<DT, 8, SEL>(a, s);
+    case 10: return launch_fixed_geom<DT, 10, SEL>(a, s);
+    case 16: return launch_fixed_geom<DT, 16, SEL>(a, s);
+    default: return hipErrorInvalidValue;
     }
+}
+
+const int kGeomDims[4][2] = {{0, 0}, {64, 60}, {64, 48}, {128, 32}};
+
+bool fixed_radius(int r) {
+    return r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 8 || r == 10 || r == 16;
 }
 
 hipError_t launch_forward(int dtype, const FwdLaunch &a, hipStream_t s) {

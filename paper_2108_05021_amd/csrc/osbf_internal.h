@@ -16,7 +16,14 @@ struct FwdLaunch {
     int tw, th;           // output tile, multiples of r
     int tiles_x, tiles_y;
     int pitch, arr;       // LDS row pitch and per-array size, in floats
+    int geom;             // LDS geometry (Geom)
 };
+
+// LDS geometries: fixed regions compiled for the common radii, or the
+// generic kernel whose region follows the tile (any radius).
+enum Geom : int { GEOM_GENERIC = 0, GEOM_64x60 = 1, GEOM_64x48 = 2, GEOM_128x32 = 3 };
+extern const int kGeomDims[4][2];   // region width, height (0 for generic)
+bool fixed_radius(int r);
 
 // Output tile for an LDS region of at most RW x RH pixels (false if none).
 bool fwd_tile_shape(int RW, int RH, int r, int k, int *tw, int *th);
