@@ -95,24 +95,42 @@ double plan_cost(const Plan &p, int H, int W, int r) {
     const double lw = std::min<double>(tw + 2.0 * p.k * r, W), lh = std::min<double>(th + 2.0 * p.k * r, H);
     work += lw * lh * 0.05;
     double cost = work / ((double)p.k * tw * th);
+    // waves resident per CU: LDS-limited workgroups times waves per workgroup
     const int per_cu = (int)(163840 / std::max<size_t>(p.lds_bytes(), 1));
-    if (per_cu < 2) cost *= 1.6;
-    else if (per_cu < 3) cost *= 1.1;
+    const int waves = per_cu * (p.geom == GEOM_GENERIC ? 4 : (p.geom == GEOM_128x64 ? 16 : 8));
+    if (waves < 8) cost *= 1.8;
+    else if (waves < 12) cost *= 1.3;
+    else if (waves < 16) cost *= 1.1;
     if (p.geom == GEOM_GENERIC) cost *= 1.8;   // runtime-pitch addressing
     return cost + 0.25 / p.k;
 }
 
+// Measured defaults for the compiled radii (3x2048x2048 FP32, T=30 on
+// MI355X): 512-thread 64x48 regions up to r=8, 1024-thread 128x64 regions
+// for larger radii; fusion pays off for r <= 3.
+struct TunedShape { int r, geom, k; };
+const TunedShape kTuned[] = {{1, GEOM_64x48, 3}, {2, GEOM_64x48, 3}, {3, GEOM_64x48, 2},
+                             {4, GEOM_64x48, 1}, {5, GEOM_64x48, 1}, {8, GEOM_64x48, 1},
+                             {10, GEOM_128x64, 1}, {16, GEOM_128x64, 1}};
+
 // OSBF_PLAN="geom,k" forces a plan (tests and tuning): geom 0 is the generic
-// kernel (region chosen by cost), 1..3 the fixed geometries.
+// kernel (region chosen by cost), 1.. the fixed geometries (enum Geom).
 Plan choose_plan(int H, int W, int r, int T) {
     const size_t limit = lds_limit();
     const int kmax = T > 0 ? std::min(T, 8) : 1;
     int force_geom = -1, force_k = -1;
     if (const char *env = getenv("OSBF_PLAN")) {
-        if (sscanf(env, "%d,%d", &force_geom, &force_k) != 2 || force_geom < 0 || force_geom > 3 || force_k < 1)
+        if (sscanf(env, "%d,%d", &force_geom, &force_k) != 2 || force_geom < 0 || force_geom >= NUM_GEOMS || force_k < 1)
             force_geom = force_k = -1;
         else
             force_k = std::min(force_k, kmax);
+    }
+    if (force_geom < 0) {
+        for (const auto &t : kTuned) {
+            if (t.r != r) continue;
+            Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
+            if (p.tw && p.lds_bytes() <= limit) return p;
+        }
     }
     Plan best;
     double best_cost = 1e300;
@@ -124,7 +142,7 @@ Plan choose_plan(int H, int W, int r, int T) {
     for (int k = 1; k <= kmax; ++k) {
         if (force_k > 0 && k != force_k) continue;
         if (fixed_radius(r))
-            for (int g = 1; g <= 3; ++g)
+            for (int g = 1; g < NUM_GEOMS; ++g)
                 if (force_geom < 0 || force_geom == g)
                     consider(make_plan(g, kGeomDims[g][0], kGeomDims[g][1], r, k));
         if (force_geom <= 0)
@@ -133,7 +151,7 @@ Plan choose_plan(int H, int W, int r, int T) {
     if (!best.tw && force_geom >= 0) {   // forced plan does not fit: fall back to the model
         for (int k = 1; k <= kmax; ++k) {
             if (fixed_radius(r))
-                for (int g = 1; g <= 3; ++g) consider(make_plan(g, kGeomDims[g][0], kGeomDims[g][1], r, k));
+                for (int g = 1; g < NUM_GEOMS; ++g) consider(make_plan(g, kGeomDims[g][0], kGeomDims[g][1], r, k));
             for (const auto &reg : kRegions) consider(make_plan(GEOM_GENERIC, reg[0], reg[1], r, k));
         }
     }

@@ -258,11 +258,11 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(FwdLaunch a) {
 // Phase A of the fixed-geometry kernel: V on columns [max(0,xa-R),
 // min(W,xb+R)), rows [ya, yb+R), in blocks of R rows anchored at multiples of
 // R.  Each lane owns one region column; a block's 2R input rows are read once.
-template <int R, int RW, int RH, bool CL>
+template <int R, int RW, int RH, int NT, bool CL>
 __device__ __forceinline__ void fixed_phase_v(const float *P, float *V, int lx, int ly, int ox,
                                               int oy, int H, int W, int xa, int xb, int ya, int yb) {
     constexpr int PITCH = RW + 1;
-    constexpr int NY = 256 / RW;
+    constexpr int NY = NT / RW;
     const int x = ox + lx;
     if (x < max(0, xa - R) || x >= min(W, xb + R)) return;
     const int yend = yb + R;
@@ -303,17 +303,18 @@ __device__ __forceinline__ void fixed_phase_v(const float *P, float *V, int lx, 
 
 // Phase B of the fixed-geometry kernel: Q on columns [xa, xb+R), rows
 // [ya, yb+R); H on the same columns, rows [ya, yb).  One lane per region row.
-template <int R, int RW, int RH, bool CL>
+template <int R, int RW, int RH, int NT, bool CL>
 __device__ __forceinline__ void fixed_phase_qh(const float *P, const float *V, float *Q, float *Hs,
                                                int lr, int lb, int ox, int oy, int W, int xa,
                                                int xb, int ya, int yb) {
     constexpr int PITCH = RW + 1;
+    constexpr int NB = NT / 64;  // lane groups over column blocks
     const int y = oy + lr;
     if (lr >= RH || y < ya || y >= yb + R) return;
     const bool doH = y < yb;
     const int xend = xb + R;
     const int nblk = (xend - xa + R - 1) / R;
-    for (int b = lb; b < nblk; b += 4) {
+    for (int b = lb; b < nblk; b += NB) {
         const int x0 = xa + b * R;
         float v[2 * R], p[2 * R];
         if (!CL) {
@@ -369,14 +370,15 @@ __device__ __forceinline__ void fixed_phase_qh(const float *P, const float *V, f
 // immediate offset from one base address; one wave spans a region row.  The
 // arithmetic is the same sequence of FP32 operations as fwd_tile (same block
 // anchors, same summation order), so both kernels give identical bits.
-template <int DT, int R, int RW, int RH, bool SEL>
+template <int DT, int R, int RW, int RH, int NT, bool SEL>
 __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int tile_y, int plane,
                                           float *lds) {
     using S = Storage<DT>;
     constexpr int PITCH = RW + 1;
     constexpr int ARR = RH * PITCH;
-    constexpr int NY = 256 / RW;  // waves stacked vertically
+    constexpr int NY = NT / RW;  // region rows handled at once
     static_assert(RW == 64 || RW == 128, "region width");
+    static_assert(NT % RW == 0 && NT % 64 == 0, "thread count");
     static_assert(RH <= 64, "phase B maps one lane per region row");
     float *const P = lds;
     float *const V = lds + ARR;
@@ -416,13 +418,13 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
         const int ya = max(0, Y0 - e), yb = min(H, Y0 + TH + e);
 
         if (interior) {
-            fixed_phase_v<R, RW, RH, false>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
+            fixed_phase_v<R, RW, RH, NT, false>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
             __syncthreads();
-            fixed_phase_qh<R, RW, RH, false>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
+            fixed_phase_qh<R, RW, RH, NT, false>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
         } else {
-            fixed_phase_v<R, RW, RH, true>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
+            fixed_phase_v<R, RW, RH, NT, true>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
             __syncthreads();
-            fixed_phase_qh<R, RW, RH, true>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
+            fixed_phase_qh<R, RW, RH, NT, true>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
         }
         __syncthreads();
 
@@ -467,14 +469,14 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
     }
 }
 
-template <int DT, int R, int RW, int RH, bool SEL>
-__global__ __launch_bounds__(256) void fwd_fixed_kernel(FwdLaunch a) {
+template <int DT, int R, int RW, int RH, int NT, bool SEL>
+__global__ __launch_bounds__(NT) void fwd_fixed_kernel(FwdLaunch a) {
     extern __shared__ float lds[];
     const int ntiles = a.tiles_x * a.tiles_y;
     const int total = ntiles * a.planes;
     const int t = xcd_remap(blockIdx.x, total);
     const int plane = t / ntiles, tile = t - plane * ntiles;
-    fwd_fixed<DT, R, RW, RH, SEL>(a, tile % a.tiles_x, tile / a.tiles_x, plane, lds);
+    fwd_fixed<DT, R, RW, RH, NT, SEL>(a, tile % a.tiles_x, tile / a.tiles_x, plane, lds);
 }
 
 template <int DT, int R, bool SEL>
@@ -491,32 +493,38 @@ template <int DT, int R, bool SEL>
     return hipGetLastError();
 }
 
-template <int DT, int R, int RW, int RH, bool SEL>
+template <int DT, int R, int RW, int RH, int NT, bool SEL>
 static hipError_t launch_fixed(const FwdLaunch &a, hipStream_t stream) {
     const size_t lds = (size_t)4 * RH * (RW + 1) * sizeof(float);
-    auto kern = fwd_fixed_kernel<DT, R, RW, RH, SEL>;
+    auto kern = fwd_fixed_kernel<DT, R, RW, RH, NT, SEL>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const int blocks = a.tiles_x * a.tiles_y * a.planes;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, stream, a);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, stream, a);
     return hipGetLastError();
 }
 
 template <int DT, int R, bool SEL>
 static hipError_t launch_fixed_geom(const FwdLaunch &a, hipStream_t s) {
     switch (a.geom) {
-    case GEOM_64x60: return launch_fixed<DT, R, 64, 60, SEL>(a, s);
-    case GEOM_64x48: return launch_fixed<DT, R, 64, 48, SEL>(a, s);
-    case GEOM_128x32: return launch_fixed<DT, R, 128, 32, SEL>(a, s);
+    case GEOM_64x48: return launch_fixed<DT, R, 64, 48, 512, SEL>(a, s);
+    case GEOM_64x32: return launch_fixed<DT, R, 64, 32, 512, SEL>(a, s);
+    case GEOM_64x60: return launch_fixed<DT, R, 64, 60, 512, SEL>(a, s);
+    case GEOM_128x64: return launch_fixed<DT, R, 128, 64, 1024, SEL>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
+// Selection maps are a training-path feature (FP32 only), so reduced-precision
+// launches with maps take the generic kernel (it accepts any layout that fits).
 template <int DT, bool SEL>
 static hipError_t launch_fwd_r(const FwdLaunch &a, hipStream_t s) {
+    if constexpr (SEL && DT != DT_F32) {
+        return launch_fwd<DT, 0, SEL>(a, s);
+    } else {
     if (a.geom == GEOM_GENERIC) return launch_fwd<DT, 0, SEL>(a, s);
     switch (a.r) {
     case 1: return launch_fixed_geom<DT, 1, SEL>(a, s);
@@ -529,9 +537,10 @@ static hipError_t launch_fwd_r(const FwdLaunch &a, hipStream_t s) {
     case 16: return launch_fixed_geom<DT, 16, SEL>(a, s);
     default: return hipErrorInvalidValue;
     }
+    }
 }
 
-const int kGeomDims[4][2] = {{0, 0}, {64, 60}, {64, 48}, {128, 32}};
+const int kGeomDims[NUM_GEOMS][2] = {{0, 0}, {64, 48}, {64, 32}, {64, 60}, {128, 64}};
 
 bool fixed_radius(int r) {
     return r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 8 || r == 10 || r == 16;

@@ -21,8 +21,9 @@ struct FwdLaunch {
 
 // LDS geometries: fixed regions compiled for the common radii, or the
 // generic kernel whose region follows the tile (any radius).
-enum Geom : int { GEOM_GENERIC = 0, GEOM_64x60 = 1, GEOM_64x48 = 2, GEOM_128x32 = 3 };
-extern const int kGeomDims[4][2];   // region width, height (0 for generic)
+enum Geom : int { GEOM_GENERIC = 0, GEOM_64x48 = 1, GEOM_64x32 = 2, GEOM_64x60 = 3, GEOM_128x64 = 4,
+                  NUM_GEOMS = 5 };
+extern const int kGeomDims[NUM_GEOMS][2];   // region width, height (0 for generic)
 bool fixed_radius(int r);
 
 // Output tile for an LDS region of at most RW x RH pixels (false if none).
