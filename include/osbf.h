@@ -112,6 +112,37 @@ osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t hei
                          void *ckpt, int32_t ck, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Workspace bytes osbf_backward needs: one FP32 plane set for the gradient
+ * ping-pong, plus (checkpoint mode, ck > 0) two FP32 plane sets and
+ * min(ck, T) uint8 maps for recomputing one segment.  (size_t)-1 if invalid.
+ */
+size_t osbf_backward_workspace_size(int32_t planes, int32_t height, int32_t width,
+                                    int32_t radius, int32_t iterations, int32_t ck);
+
+/*
+ * osbf_backward -- gradient of T sweeps with every selection held at its
+ * forward value (the filter is piecewise linear in the image; away from ties
+ * this is its exact derivative).  Each sweep's transpose scatters the
+ * upstream gradient of a pixel, divided by the size of its selected window,
+ * over that window's clamped pixels; it is computed as a gather (no atomics).
+ *
+ *   grad_out   device FP32 [planes][H][W], gradient w.r.t. the output U^T.
+ *   grad_in    device FP32 [planes][H][W], gradient w.r.t. the input U^0;
+ *              may equal grad_out.
+ *   sel        device uint8 [T][planes][H][W] maps from an FP32 osbf_forward,
+ *     or
+ *   ckpt, ck   the checkpoints [ceil(T/ck)][planes][H][W] and interval of an
+ *              FP32 osbf_forward; each segment's maps are recomputed with the
+ *              forward's own kernels (bit-identical to the original maps).
+ *              Exactly one of sel / ckpt must be non-NULL (unless T or r is 0).
+ *   ws         device workspace >= osbf_backward_workspace_size(..., ck or 0).
+ */
+osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes, int32_t height,
+                          int32_t width, int32_t radius, int32_t iterations,
+                          osbf_boundary boundary, const uint8_t *sel, const float *ckpt,
+                          int32_t ck, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * osbf_forward_plan -- the launch plan osbf_forward uses for these arguments
  * (for profiling and tests; no device work).  Writes the output tile shape,
  * the sweeps fused per launch and the number of kernel launches (per chunk

@@ -174,6 +174,53 @@ std::vector<Launch> make_launches(int T, int ck, int k) {
     return v;
 }
 
+// Enqueue one forward launch (k sweeps from t0) over every plane, chunked so
+// the grid stays within 2^31 workgroups.  `sel_t0` is the map of sweep t0,
+// plane 0 (nullable); consecutive sweeps' maps are plane_set apart.
+hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, uint8_t *sel_t0,
+                           int planes, int H, int W, int r, osbf_dtype dtype, hipStream_t stream) {
+    const size_t plane_set = (size_t)planes * H * W;
+    const int tiles_x = (W + plan.tw - 1) / plan.tw, tiles_y = (H + plan.th - 1) / plan.th;
+    const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)tiles_x * tiles_y)));
+    for (int p0 = 0; p0 < planes; p0 += max_planes) {
+        const int np = std::min(max_planes, planes - p0);
+        const size_t off = (size_t)p0 * H * W;
+        FwdLaunch a;
+        a.src = (const char *)in + off * elem_bytes(dtype);
+        a.dst = (char *)out + off * elem_bytes(dtype);
+        a.sel = sel_t0 ? sel_t0 + off : nullptr;
+        a.sel_stride = (long long)plane_set;
+        a.planes = np;
+        a.H = H; a.W = W; a.r = r; a.k = k;
+        a.tw = plan.tw; a.th = plan.th;
+        a.tiles_x = tiles_x; a.tiles_y = tiles_y;
+        a.geom = plan.geom;
+        if (plan.geom == GEOM_GENERIC)
+            fwd_lds_layout(plan.tw, plan.th, r, k, &a.pitch, &a.arr);
+        else
+            a.pitch = plan.pitch, a.arr = plan.arr;
+        hipError_t e = launch_forward((int)dtype, a, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Tile of the adjoint kernel: the largest multiple of r whose 2r-grown
+// region fits the smallest of 64/80/96/128 pixels that leaves a tile, within
+// the device's LDS.
+bool adjoint_tile(int r, int *tw, int *th, int *pitch, int *arr) {
+    for (int reg : {64, 80, 96, 128}) {
+        const int t = ((reg - 4 * r) / r) * r;
+        if (t < std::max(r, 4)) continue;
+        bwd_lds_layout(t, t, r, pitch, arr);
+        if ((size_t)5 * (*arr) * sizeof(float) <= lds_limit()) {
+            *tw = *th = t;
+            return true;
+        }
+    }
+    return false;
+}
+
 osbf_status check_sizes(int32_t planes, int32_t H, int32_t W, int dtype, int32_t r, int32_t T) {
     if (planes < 1 || H < 1 || W < 1)
         return fail(OSBF_ERROR_INVALID_VALUE, "planes, height and width must be >= 1 (got %d, %d, %d)",
@@ -257,8 +304,6 @@ osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t H, 
             return hip_fail(e, "copy to workspace");
         cur = ws;
     }
-    const int tiles_x = (W + plan.tw - 1) / plan.tw, tiles_y = (H + plan.th - 1) / plan.th;
-    const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)tiles_x * tiles_y)));
     for (int i = 0; i < nl; ++i) {
         void *out = ((nl - 1 - i) % 2 == 0) ? dst : ws;
         if (nck && launches[i].t0 % ck == 0) {
@@ -266,27 +311,115 @@ osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t H, 
             if ((e = hipMemcpyAsync((char *)ckpt + s * bytes, cur, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
                 return hip_fail(e, "copy checkpoint");
         }
-        for (int p0 = 0; p0 < planes; p0 += max_planes) {
-            const int np = std::min(max_planes, planes - p0);
-            const size_t off = (size_t)p0 * H * W;
-            FwdLaunch a;
-            a.src = (const char *)cur + off * elem_bytes(dtype);
-            a.dst = (char *)out + off * elem_bytes(dtype);
-            a.sel = sel ? sel + (size_t)launches[i].t0 * plane_set + off : nullptr;
-            a.sel_stride = (long long)plane_set;
-            a.planes = np;
-            a.H = H; a.W = W; a.r = r; a.k = launches[i].k;
-            a.tw = plan.tw; a.th = plan.th;
-            a.tiles_x = tiles_x; a.tiles_y = tiles_y;
-            a.geom = plan.geom;
-            if (plan.geom == GEOM_GENERIC)
-                fwd_lds_layout(plan.tw, plan.th, r, a.k, &a.pitch, &a.arr);
-            else
-                a.pitch = plan.pitch, a.arr = plan.arr;
-            if ((e = launch_forward((int)dtype, a, stream)) != hipSuccess)
-                return hip_fail(e, "forward launch");
-        }
+        uint8_t *sel_t0 = sel ? sel + (size_t)launches[i].t0 * plane_set : nullptr;
+        if ((e = enqueue_forward(plan, launches[i].k, cur, out, sel_t0, planes, H, W, r, dtype, stream)) != hipSuccess)
+            return hip_fail(e, "forward launch");
         cur = out;
+    }
+    return OSBF_SUCCESS;
+}
+
+size_t osbf_backward_workspace_size(int32_t planes, int32_t H, int32_t W, int32_t r, int32_t T,
+                                    int32_t ck) {
+    if (check_sizes(planes, H, W, OSBF_F32, r, T) != OSBF_SUCCESS || ck < 0) return (size_t)-1;
+    if (T == 0 || r == 0) return 0;
+    const size_t P = (size_t)planes * H * W;
+    size_t n = P * sizeof(float);                        // gradient ping-pong
+    if (ck > 0) n += 2 * P * sizeof(float) + (size_t)std::min(ck, T) * P;  // recompute buffers, maps
+    return n;
+}
+
+osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes, int32_t H,
+                          int32_t W, int32_t r, int32_t T, osbf_boundary boundary,
+                          const uint8_t *sel, const float *ckpt, int32_t ck, void *ws,
+                          size_t ws_bytes, void *stream_) {
+    g_last_error.clear();
+    osbf_status st = check_sizes(planes, H, W, OSBF_F32, r, T);
+    if (st != OSBF_SUCCESS) return st;
+    if (boundary != OSBF_BOUNDARY_REPLICATE)
+        return fail(OSBF_ERROR_INVALID_VALUE, "unknown boundary %d", (int)boundary);
+    if (!grad_out || !grad_in) return fail(OSBF_ERROR_INVALID_VALUE, "gradients must be non-NULL");
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t P = (size_t)planes * H * W;
+    const size_t gbytes = P * sizeof(float);
+    hipError_t e;
+    if (T == 0 || r == 0) {  // identity map
+        if (grad_in != grad_out &&
+            (e = hipMemcpyAsync(grad_in, grad_out, gbytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy");
+        return OSBF_SUCCESS;
+    }
+    if ((sel == nullptr) == (ckpt == nullptr))
+        return fail(OSBF_ERROR_INVALID_VALUE, "pass exactly one of sel (all maps) or ckpt (checkpoints)");
+    if (ckpt && ck < 1) return fail(OSBF_ERROR_INVALID_VALUE, "checkpoint interval %d < 1", ck);
+    const size_t need = osbf_backward_workspace_size(planes, H, W, r, T, ckpt ? ck : 0);
+    if (!ws || ws_bytes < need)
+        return fail(OSBF_ERROR_WORKSPACE, "workspace of %zu bytes required, got %zu", need, ws ? ws_bytes : 0);
+
+    BwdLaunch b;
+    if (!adjoint_tile(r, &b.tw, &b.th, &b.pitch, &b.arr))
+        return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
+    b.H = H; b.W = W; b.r = r;
+    b.tiles_x = (W + b.tw - 1) / b.tw;
+    b.tiles_y = (H + b.th - 1) / b.th;
+    const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)b.tiles_x * b.tiles_y)));
+
+    float *wsg = (float *)ws;
+    float *f1 = nullptr, *f2 = nullptr;
+    uint8_t *wsel = nullptr;
+    if (ckpt) {
+        f1 = wsg + P;
+        f2 = f1 + P;
+        wsel = (uint8_t *)(f2 + P);
+    }
+    // sweep t = T-1 .. 0; the last one (t = 0) writes grad_in
+    const float *gin = grad_out;
+    if (grad_out == grad_in && (T % 2) == 1) {
+        if ((e = hipMemcpyAsync(wsg, grad_out, gbytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy to workspace");
+        gin = wsg;
+    }
+    auto adjoint = [&](int t, const uint8_t *sel_t) -> hipError_t {
+        float *gout = (t % 2 == 0) ? grad_in : wsg;
+        for (int p0 = 0; p0 < planes; p0 += max_planes) {
+            const size_t off = (size_t)p0 * H * W;
+            b.planes = std::min(max_planes, planes - p0);
+            b.gnext = gin + off;
+            b.sel = sel_t + off;
+            b.g = gout + off;
+            hipError_t err = launch_adjoint(b, stream);
+            if (err != hipSuccess) return err;
+        }
+        gin = gout;
+        return hipSuccess;
+    };
+
+    if (sel) {
+        for (int t = T - 1; t >= 0; --t)
+            if ((e = adjoint(t, sel + (size_t)t * P)) != hipSuccess) return hip_fail(e, "adjoint launch");
+        return OSBF_SUCCESS;
+    }
+    // Checkpoint mode: recompute each segment's maps with the forward's own
+    // launches (bit-identical maps), then run that segment's adjoints.
+    const Plan plan = choose_plan(H, W, r, T);
+    if (!plan.tw) return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
+    const std::vector<Launch> launches = make_launches(T, ck, plan.k);
+    const int nseg = (T + ck - 1) / ck;
+    for (int sidx = nseg - 1; sidx >= 0; --sidx) {
+        const int s0 = sidx * ck, s1 = std::min(T, s0 + ck);
+        const void *cur = ckpt + (size_t)sidx * P;
+        bool use_f1 = true;
+        for (const Launch &L : launches) {
+            if (L.t0 < s0 || L.t0 >= s1) continue;
+            float *out = use_f1 ? f1 : f2;
+            use_f1 = !use_f1;
+            if ((e = enqueue_forward(plan, L.k, cur, out, wsel + (size_t)(L.t0 - s0) * P, planes, H, W,
+                                     r, OSBF_F32, stream)) != hipSuccess)
+                return hip_fail(e, "forward recompute");
+            cur = out;
+        }
+        for (int t = s1 - 1; t >= s0; --t)
+            if ((e = adjoint(t, wsel + (size_t)(t - s0) * P)) != hipSuccess) return hip_fail(e, "adjoint launch");
     }
     return OSBF_SUCCESS;
 }

@@ -31,4 +31,17 @@ bool fwd_tile_shape(int RW, int RH, int r, int k, int *tw, int *th);
 void fwd_lds_layout(int tw, int th, int r, int k, int *pitch, int *arr);
 hipError_t launch_forward(int dtype, const FwdLaunch &a, hipStream_t s);
 
+// One launch of the adjoint kernel: G = A_t^T Gnext for every plane.
+struct BwdLaunch {
+    const float *gnext;   // [planes][H][W] upstream gradient G^{t+1}
+    const uint8_t *sel;   // [planes][H][W] selection map of forward sweep t
+    float *g;             // [planes][H][W] G^t, never aliases gnext
+    int planes, H, W, r;
+    int tw, th, tiles_x, tiles_y;
+    int pitch, arr;       // LDS layout (bwd_lds_layout)
+};
+
+void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr);
+hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t s);
+
 }  // namespace osbf

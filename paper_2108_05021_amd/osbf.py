@@ -49,6 +49,10 @@ def lib():
     L.osbf_forward.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int,
                                vp, vp, i32, vp, sz, vp]
     L.osbf_forward.restype = ctypes.c_int
+    L.osbf_backward_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32]
+    L.osbf_backward_workspace_size.restype = sz
+    L.osbf_backward.argtypes = [vp, vp, i32, i32, i32, i32, i32, ctypes.c_int, vp, vp, i32, vp, sz, vp]
+    L.osbf_backward.restype = ctypes.c_int
     L.osbf_forward_plan.argtypes = [i32, i32, i32, ctypes.c_int, i32, i32, i32] + [ctypes.POINTER(i32)] * 4
     L.osbf_forward_plan.restype = ctypes.c_int
     _lib = L
@@ -123,3 +127,62 @@ def forward(x: torch.Tensor, r: int, T: int, *, return_sel: bool = False,
     if ckpt is not None:
         res.append(ckpt)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def backward_workspace_size(planes, H, W, r, T, ck: int = 0) -> int:
+    return int(lib().osbf_backward_workspace_size(planes, H, W, r, T, ck))
+
+
+def osbf_backward(grad_out, grad_in, r: int, T: int, *, sel=None, ckpt=None, ck: int = 0, ws=None):
+    """Direct call of the C entry point on preallocated FP32 tensors."""
+    planes, H, W = _geometry(grad_out)
+    status = lib().osbf_backward(
+        _ptr(grad_out), _ptr(grad_in), planes, H, W, r, T, 0, _ptr(sel), _ptr(ckpt), ck,
+        _ptr(ws), 0 if ws is None else ws.numel() * ws.element_size(), _stream(grad_out.device))
+    _check(status)
+
+
+def backward(grad_out: torch.Tensor, r: int, T: int, *, sel=None, ckpt=None, ck: int = 0):
+    """Gradient w.r.t. the input of T sweeps, given the forward's selection
+    maps ``sel`` [T, ...] or its checkpoints ``ckpt`` taken every ``ck`` sweeps."""
+    planes, H, W = _geometry(grad_out)
+    grad_in = torch.empty_like(grad_out)
+    n = backward_workspace_size(planes, H, W, r, T, ck if ckpt is not None else 0)
+    ws = torch.empty(max(n, 1), dtype=torch.uint8, device=grad_out.device) if n else None
+    osbf_backward(grad_out, grad_in, r, T, sel=sel, ckpt=ckpt, ck=ck, ws=ws)
+    return grad_in
+
+
+class OSBFFunction(torch.autograd.Function):
+    """Differentiable one-sided box filter (FP32).  The backward holds every
+    selection at its forward value; ``ckpt_every`` > 0 stores iterates every
+    that many sweeps instead of all T uint8 selection maps."""
+
+    @staticmethod
+    def forward(ctx, x, r: int, T: int, ckpt_every: int = 0):
+        x = x.contiguous()
+        if ckpt_every > 0:
+            y, ck = forward(x, r, T, ckpt_every=ckpt_every)
+            ctx.save_for_backward(ck)
+            ctx.mode = "ckpt"
+        else:
+            y, sel = forward(x, r, T, return_sel=True)
+            ctx.save_for_backward(sel)
+            ctx.mode = "sel"
+        ctx.r, ctx.T, ctx.ck = r, T, ckpt_every
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        (saved,) = ctx.saved_tensors
+        gy = gy.contiguous().float()
+        if ctx.mode == "ckpt":
+            gx = backward(gy, ctx.r, ctx.T, ckpt=saved, ck=ctx.ck)
+        else:
+            gx = backward(gy, ctx.r, ctx.T, sel=saved)
+        return gx, None, None, None
+
+
+def osbf(x: torch.Tensor, r: int, T: int, ckpt_every: int = 0) -> torch.Tensor:
+    """The filter as a differentiable op (see OSBFFunction)."""
+    return OSBFFunction.apply(x, r, T, ckpt_every)

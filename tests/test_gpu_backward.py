@@ -1,0 +1,146 @@
+"""GPU parity of the adjoint (osbf_backward) against the FP64 oracle.
+
+The adjoint is compared on the GPU forward's own selection maps, so near-tie
+flips between FP32 and FP64 do not enter: the oracle's scatter-form adjoint
+with those maps is the exact reference.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_05021_amd import osbf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+def _tol(g):
+    return 1e-5 * float(np.abs(g).max()) + 1e-7
+
+
+@pytest.mark.parametrize("shape", [(1, 150, 197), (2, 67, 300), (3, 33, 45), (1, 1, 50), (1, 50, 1), (1, 1, 1),
+                                   (1, 7, 7)])
+@pytest.mark.parametrize("r", [1, 2, 3, 5, 8, 13, 16])
+def test_single_adjoint_sweep(dev, shape, r):
+    rng = np.random.default_rng(hash((shape, r)) % 2**32)
+    img = synth.voronoi(shape[1], shape[2], 6, 0.05, rng, C=shape[0])
+    x = _gpu(img, dev)
+    _, sel = osbf.forward(x, r, 1, return_sel=True)
+    g = rng.normal(size=img.shape).astype(np.float32)
+    gx = osbf.backward(_gpu(g, dev), r, 1, sel=sel).cpu().numpy()
+    s = sel[0].cpu().numpy().reshape(-1, shape[1], shape[2])
+    gp = g.reshape(-1, shape[1], shape[2])
+    want = np.stack([oracle.adjoint(gp[p].astype(np.float64), s[p], r) for p in range(gp.shape[0])])
+    np.testing.assert_allclose(gx.reshape(want.shape), want, rtol=0, atol=_tol(want))
+
+
+@pytest.mark.parametrize("r", [1, 3, 6])
+def test_dot_product_and_mass(dev, r):
+    """<A x, y> (oracle, FP64) = <x, A^T y> (GPU) and sum(A^T y) = sum(y)."""
+    rng = np.random.default_rng(10 + r)
+    img = synth.voronoi(96, 130, 8, 0.05, rng, C=1)
+    _, sel = osbf.forward(_gpu(img, dev), r, 1, return_sel=True)
+    s = sel[0, 0].cpu().numpy()
+    xv = rng.normal(size=(96, 130))
+    yv = rng.normal(size=(96, 130)).astype(np.float32)
+    aty = osbf.backward(_gpu(yv[None], dev), r, 1, sel=sel).cpu().numpy()[0].astype(np.float64)
+    lhs = np.sum(oracle.apply_fixed(xv, s, r) * yv)
+    rhs = np.sum(xv * aty)
+    assert rhs == pytest.approx(lhs, rel=1e-5)
+    assert aty.sum() == pytest.approx(float(yv.astype(np.float64).sum()), rel=1e-5, abs=1e-3)
+
+
+@pytest.mark.parametrize("r,T", [(1, 4), (3, 10), (5, 3)])
+def test_full_backward_against_oracle_chain(dev, r, T):
+    """T adjoint sweeps on the GPU forward's maps equal the oracle's chain of
+    adjoints on the same maps; checkpoint mode recomputes bit-identical maps,
+    so it matches the map mode exactly."""
+    rng = np.random.default_rng(20 + r)
+    img = synth.voronoi(120, 111, 10, 0.05, rng, C=2)
+    x = _gpu(img, dev)
+    w = rng.normal(size=img.shape).astype(np.float32)
+    _, sel = osbf.forward(x, r, T, return_sel=True)
+    g_sel = osbf.backward(_gpu(w, dev), r, T, sel=sel)
+    for ck in (1, 3, T):
+        _, ckpt = osbf.forward(x, r, T, ckpt_every=ck)
+        g_ck = osbf.backward(_gpu(w, dev), r, T, ckpt=ckpt, ck=ck)
+        assert torch.equal(g_ck, g_sel), f"checkpoint every {ck} differs from stored maps"
+    sn = sel.cpu().numpy()
+    for p in range(2):
+        g = w[p].astype(np.float64)
+        for t in range(T - 1, -1, -1):
+            g = oracle.adjoint(g, sn[t, p], r)
+        np.testing.assert_allclose(g_sel[p].cpu().numpy(), g, rtol=0, atol=1e-5 * np.abs(g).max() + 1e-6)
+
+
+def test_large_radius_is_reported(dev):
+    x = torch.rand(1, 64, 64, device=dev)
+    _, sel = osbf.forward(x, 24, 1, return_sel=True)
+    with pytest.raises(osbf.OsbfError) as ei:
+        osbf.backward(x, 24, 1, sel=sel)
+    assert ei.value.status == 2
+
+
+def test_in_place_and_identity(dev):
+    rng = np.random.default_rng(30)
+    img = synth.voronoi(64, 70, 6, 0.05, rng, C=1)
+    x = _gpu(img, dev)
+    w = _gpu(rng.normal(size=img.shape), dev)
+    for T in (1, 2, 3):
+        _, sel = osbf.forward(x, 2, T, return_sel=True)
+        want = osbf.backward(w, 2, T, sel=sel)
+        z = w.clone()
+        ws = torch.empty(osbf.backward_workspace_size(1, 64, 70, 2, T), dtype=torch.uint8, device=dev)
+        osbf.osbf_backward(z, z, 2, T, sel=sel, ws=ws)
+        assert torch.equal(z, want)
+    assert torch.equal(osbf.backward(w, 0, 3, sel=None), w)
+    assert torch.equal(osbf.backward(w, 2, 0, sel=None), w)
+
+
+def test_autograd_function(dev):
+    rng = np.random.default_rng(40)
+    img = synth.voronoi(80, 90, 8, 0.05, rng, C=3)
+    w = _gpu(rng.normal(size=img.shape), dev)
+    for ck in (0, 2):
+        x = _gpu(img, dev).requires_grad_(True)
+        y = osbf.osbf(x, 3, 5, ck)
+        (w * y).sum().backward()
+        _, sel = osbf.forward(x.detach(), 3, 5, return_sel=True)
+        assert torch.equal(x.grad, osbf.backward(w, 3, 5, sel=sel))
+        assert torch.equal(y.detach(), osbf.forward(x.detach(), 3, 5))
+
+
+def test_finite_differences_on_crops(dev):
+    """FD check on 32x32 crops of the 512x512 differentiation workload: at
+    pixels where +-h changes no selection map (FP64 oracle), the central
+    difference of sum(W * filter) equals the GPU gradient."""
+    rng = np.random.default_rng(50)
+    full = synth.voronoi(512, 512, 64, 0.05, np.random.default_rng(5), C=1)[0]
+    r, T = 3, 10
+    checked = 0
+    for (y0, x0) in [(0, 0), (200, 310), (480, 480)]:
+        crop = full[y0:y0 + 32, x0:x0 + 32].astype(np.float64)
+        w = rng.normal(size=crop.shape)
+        xg = _gpu(crop[None], dev).requires_grad_(True)
+        (osbf.osbf(xg, r, T) * _gpu(w[None], dev)).sum().backward()
+        grad = xg.grad[0].cpu().numpy()
+        _, sel = oracle.forward(crop, r, T, return_sel=True)
+        gsel = osbf.forward(_gpu(crop[None], dev), r, T, return_sel=True)[1].cpu().numpy()[:, 0]
+        h = 1e-5
+        for (yy, xx) in [(0, 0), (16, 16), (31, 31), (5, 27), (20, 3)]:
+            xp, xm = crop.copy(), crop.copy()
+            xp[yy, xx] += h
+            xm[yy, xx] -= h
+            yp, sp = oracle.forward(xp, r, T, return_sel=True)
+            ym, sm = oracle.forward(xm, r, T, return_sel=True)
+            stable = np.array_equal(sp, sel) and np.array_equal(sm, sel) and np.array_equal(gsel, sel[:, 0])
+            if not stable:
+                continue
+            fd = (np.sum(w * yp) - np.sum(w * ym)) / (2 * h)
+            assert grad[yy, xx] == pytest.approx(fd, rel=1e-4, abs=1e-5)
+            checked += 1
+    assert checked >= 5

@@ -299,3 +299,73 @@ def test_flip_and_transpose_equivariance():
     np.testing.assert_allclose(oracle.forward(img[:, ::-1], r, T), out[:, ::-1], atol=1e-13)
     np.testing.assert_allclose(oracle.forward(img[::-1, :], r, T), out[::-1, :], atol=1e-13)
     np.testing.assert_allclose(oracle.forward(img.T.copy(), r, T), out.T, atol=1e-13)
+
+
+# ------------------------------------------------------------ adjoint pins
+
+@pytest.mark.parametrize("seed,H,W,r", [(70, 9, 11, 1), (71, 13, 7, 2), (72, 6, 6, 3), (73, 1, 9, 2), (74, 8, 1, 1)])
+def test_adjoint_dot_product(seed, H, W, r):
+    """<A x, y> = <x, A^T y> for the sweep with its selection held fixed."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((H, W))
+    _, sel, _ = oracle.sweep(u, r)
+    x, y = rng.normal(size=(H, W)), rng.normal(size=(H, W))
+    lhs = float(np.sum(oracle.apply_fixed(x, sel, r) * y))
+    rhs = float(np.sum(x * oracle.adjoint(y, sel, r)))
+    assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-12)
+
+
+def test_adjoint_dense_matrix():
+    """The adjoint equals the transpose of the forward map's dense matrix,
+    built column by column from unit images."""
+    rng = np.random.default_rng(75)
+    H, W, r = 5, 6, 2
+    u = rng.random((H, W))
+    _, sel, _ = oracle.sweep(u, r)
+    n = H * W
+    A = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        A[:, j] = oracle.apply_fixed(e.reshape(H, W), sel, r).ravel()
+    # every row of A averages one window: non-negative, sums to one
+    assert (A >= 0).all()
+    np.testing.assert_allclose(A.sum(axis=1), 1.0, atol=1e-14)
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        np.testing.assert_allclose(oracle.adjoint(e.reshape(H, W), sel, r).ravel(), A[j], atol=1e-14)
+
+
+def test_adjoint_conserves_mass():
+    rng = np.random.default_rng(76)
+    u = rng.random((12, 10))
+    _, sel, _ = oracle.sweep(u, 3)
+    g = rng.normal(size=u.shape)
+    assert oracle.adjoint(g, sel, 3).sum() == pytest.approx(g.sum(), rel=1e-12)
+
+
+@pytest.mark.parametrize("seed,r,T", [(80, 1, 3), (81, 2, 2), (82, 3, 2)])
+def test_backward_matches_finite_differences(seed, r, T):
+    """The filter is piecewise linear in its input: where a +-h perturbation
+    of a pixel changes no selection map, the central difference of
+    sum(w * filter(x)) equals the gradient up to FP64 rounding."""
+    rng = np.random.default_rng(seed)
+    H, W = 10, 9
+    x = rng.random((H, W))
+    w = rng.normal(size=(H, W))
+    grad, sel = oracle.backward(x, w, r, T, return_sel=True)
+    h = 1e-6
+    checked = 0
+    for (yy, xx) in [(0, 0), (4, 5), (9, 8), (2, 7), (7, 1), (5, 0)]:
+        xp, xm = x.copy(), x.copy()
+        xp[yy, xx] += h
+        xm[yy, xx] -= h
+        yp, sp = oracle.forward(xp, r, T, return_sel=True)
+        ym, sm = oracle.forward(xm, r, T, return_sel=True)
+        if not (np.array_equal(sp, sel) and np.array_equal(sm, sel)):
+            continue
+        fd = (np.sum(w * yp) - np.sum(w * ym)) / (2 * h)
+        assert fd == pytest.approx(grad[yy, xx], rel=1e-6, abs=1e-8)
+        checked += 1
+    assert checked >= 3
