@@ -142,6 +142,54 @@ osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes,
                           osbf_boundary boundary, const uint8_t *sel, const float *ckpt,
                           int32_t ck, void *ws, size_t ws_bytes, void *stream);
 
+/* One image of a batch: `planes` independent H x W planes, its own radius
+ * and iteration count.  src and dst are device pointers and must differ. */
+typedef struct {
+    const void *src;
+    void *dst;
+    int32_t planes, height, width, radius, iterations;
+} osbf_image;
+
+/* A prepared batch (caller-owned plain data; see osbf_batched_prepare). */
+typedef struct {
+    int32_t n, dtype, rounds, grid;
+    int64_t max_items;       /* work items per round, upper bound */
+    int64_t total_items;     /* work items over all rounds */
+    void *ws;                /* the workspace the tables live in */
+    size_t descs_off, items_off, counts_off;
+    int32_t identity;        /* images with r = 0 or T = 0 (copied) */
+    int32_t reserved[7];
+} osbf_batch;
+
+/*
+ * Workspace bytes for a batch: one extra iterate per image (ping-pong) plus
+ * the per-round descriptor and work tables.  (size_t)-1 if invalid.
+ */
+size_t osbf_batched_workspace_size(const osbf_image *imgs, int32_t n, osbf_dtype dtype);
+
+/*
+ * osbf_batched_prepare -- plan a batch of T_j sweeps of Alg. 2 on each image
+ * (all images of one dtype, radii in {0,1,2,3,4,5,8,10,16}) and upload its
+ * tables into `ws` on `stream`.  `imgs` is host memory, read during the call.
+ * Fills `batch`.  Not capturable into a graph (it copies from host memory).
+ */
+osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype dtype,
+                                 osbf_boundary boundary, void *ws, size_t ws_bytes,
+                                 osbf_batch *batch, void *stream);
+
+/*
+ * osbf_batched_launch -- run a prepared batch: one persistent launch per
+ * round (every unfinished image advances by its fused sweep count).  Only
+ * kernel launches and device-to-device copies are enqueued, so the call can
+ * be captured into a HIP graph and replayed; each replay recomputes dst from
+ * src.  Results equal per-image osbf_forward bit for bit.
+ */
+osbf_status osbf_batched_launch(const osbf_batch *batch, void *stream);
+
+/* Prepare and launch in one call. */
+osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype,
+                         osbf_boundary boundary, void *ws, size_t ws_bytes, void *stream);
+
 /*
  * osbf_forward_plan -- the launch plan osbf_forward uses for these arguments
  * (for profiling and tests; no device work).  Writes the output tile shape,

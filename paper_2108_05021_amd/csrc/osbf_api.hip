@@ -447,3 +447,222 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t H, int32_t W, osbf_dtype d
 }
 
 }  // extern "C"
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct BatchImagePlan {
+    int k = 1, rounds = 0;
+    Plan plan;
+};
+
+// Per-image plans of a batch (64x48 fixed geometry) and the table sizes.
+struct BatchLayout {
+    std::vector<BatchImagePlan> img;
+    int rounds = 0;
+    int64_t max_items = 0, total_items = 0;
+    size_t descs_off = 0, items_off = 0, counts_off = 0, bufs_off = 0, total = 0;
+    std::vector<size_t> buf_off;
+    int identity = 0;
+};
+
+const int kBatchK[][2] = {{1, 3}, {2, 3}, {3, 2}, {4, 1}, {5, 1}, {8, 1}, {10, 1}, {16, 1}};
+
+osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchLayout *L) {
+    if (n < 0 || (n > 0 && !imgs)) return fail(OSBF_ERROR_INVALID_VALUE, "bad image list");
+    if (!valid_dtype(dtype)) return fail(OSBF_ERROR_INVALID_VALUE, "unknown dtype %d", (int)dtype);
+    L->img.resize(n);
+    L->buf_off.resize(n);
+    std::vector<int64_t> per_round;
+    for (int j = 0; j < n; ++j) {
+        const osbf_image &m = imgs[j];
+        osbf_status st = check_sizes(m.planes, m.height, m.width, dtype, m.radius, m.iterations);
+        if (st != OSBF_SUCCESS) return fail(st, "image %d: %s", j, g_last_error.c_str());
+        if (!m.src || !m.dst) return fail(OSBF_ERROR_INVALID_VALUE, "image %d: NULL pointer", j);
+        if (m.src == m.dst) return fail(OSBF_ERROR_INVALID_VALUE, "image %d: src and dst must differ", j);
+        BatchImagePlan &b = L->img[j];
+        if (m.radius == 0 || m.iterations == 0) {
+            L->identity++;
+            continue;
+        }
+        int k = 0;
+        for (const auto &t : kBatchK)
+            if (t[0] == m.radius) k = t[1];
+        if (!k) return fail(OSBF_ERROR_UNSUPPORTED, "image %d: batched radius %d not in {1,2,3,4,5,8,10,16}", j, m.radius);
+        k = std::min(k, m.iterations);
+        for (; k >= 1; --k) {
+            b.plan = make_plan(GEOM_64x48, kGeomDims[GEOM_64x48][0], kGeomDims[GEOM_64x48][1], m.radius, k);
+            if (b.plan.tw) break;
+        }
+        if (!b.plan.tw) return fail(OSBF_ERROR_UNSUPPORTED, "image %d: no tile fits", j);
+        b.k = k;
+        b.rounds = (m.iterations + k - 1) / k;
+        const int64_t tiles = (int64_t)((m.width + b.plan.tw - 1) / b.plan.tw) * ((m.height + b.plan.th - 1) / b.plan.th);
+        const int64_t items = tiles * m.planes;
+        if ((int)per_round.size() < b.rounds) per_round.resize(b.rounds, 0);
+        for (int r = 0; r < b.rounds; ++r) per_round[r] += items;
+        L->total_items += items * b.rounds;
+        L->rounds = std::max(L->rounds, b.rounds);
+    }
+    for (int64_t c : per_round) L->max_items = std::max(L->max_items, c);
+    if (L->max_items > (int64_t)INT32_MAX) return fail(OSBF_ERROR_UNSUPPORTED, "batch too large");
+    size_t off = 0;
+    L->descs_off = off;
+    off = align256(off + (size_t)L->rounds * n * sizeof(FwdLaunch));
+    L->items_off = off;
+    off = align256(off + (size_t)L->rounds * L->max_items * sizeof(uint2));
+    L->counts_off = off;
+    off = align256(off + (size_t)std::max(L->rounds, 1) * sizeof(int));
+    L->bufs_off = off;
+    for (int j = 0; j < n; ++j) {
+        L->buf_off[j] = off;
+        if (L->img[j].rounds >= 2)
+            off = align256(off + (size_t)imgs[j].planes * imgs[j].height * imgs[j].width * elem_bytes(dtype));
+    }
+    L->total = off;
+    return OSBF_SUCCESS;
+}
+
+int device_cus() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+        return 256;
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t osbf_batched_workspace_size(const osbf_image *imgs, int32_t n, osbf_dtype dtype) {
+    BatchLayout L;
+    if (batch_layout(imgs, n, dtype, &L) != OSBF_SUCCESS) return (size_t)-1;
+    return L.total;
+}
+
+osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype dtype,
+                                 osbf_boundary boundary, void *ws, size_t ws_bytes,
+                                 osbf_batch *batch, void *stream_) {
+    g_last_error.clear();
+    if (!batch) return fail(OSBF_ERROR_INVALID_VALUE, "batch must be non-NULL");
+    if (boundary != OSBF_BOUNDARY_REPLICATE)
+        return fail(OSBF_ERROR_INVALID_VALUE, "unknown boundary %d", (int)boundary);
+    BatchLayout L;
+    osbf_status st = batch_layout(imgs, n, dtype, &L);
+    if (st != OSBF_SUCCESS) return st;
+    if (L.total && (!ws || ws_bytes < L.total))
+        return fail(OSBF_ERROR_WORKSPACE, "workspace of %zu bytes required, got %zu", L.total, ws ? ws_bytes : 0);
+    hipStream_t stream = (hipStream_t)stream_;
+    // host tables
+    std::vector<FwdLaunch> descs((size_t)L.rounds * n);
+    std::vector<uint2> items((size_t)L.rounds * L.max_items);
+    std::vector<int> counts(std::max(L.rounds, 1), 0);
+    // images in decreasing cost order (fused depth, then radius) for the work lists
+    std::vector<int> order;
+    for (int j = 0; j < n; ++j)
+        if (L.img[j].rounds) order.push_back(j);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int ca = L.img[a].k * 64 + imgs[a].radius, cb = L.img[b].k * 64 + imgs[b].radius;
+        return ca > cb;
+    });
+    for (int j = 0; j < n; ++j) {
+        const BatchImagePlan &b = L.img[j];
+        const osbf_image &m = imgs[j];
+        void *buf = (char *)ws + L.buf_off[j];
+        const void *cur = m.src;
+        for (int r = 0; r < b.rounds; ++r) {
+            void *out = ((b.rounds - 1 - r) % 2 == 0) ? m.dst : buf;
+            FwdLaunch &a = descs[(size_t)r * n + j];
+            a.src = cur;
+            a.dst = out;
+            a.sel = nullptr;
+            a.sel_stride = 0;
+            a.planes = m.planes;
+            a.H = m.height; a.W = m.width; a.r = m.radius;
+            a.k = std::min(b.k, m.iterations - r * b.k);
+            a.tw = b.plan.tw; a.th = b.plan.th;
+            a.tiles_x = (m.width + b.plan.tw - 1) / b.plan.tw;
+            a.tiles_y = (m.height + b.plan.th - 1) / b.plan.th;
+            a.pitch = b.plan.pitch; a.arr = b.plan.arr;
+            a.geom = GEOM_64x48;
+            cur = out;
+        }
+    }
+    for (int r = 0; r < L.rounds; ++r) {
+        uint2 *it = items.data() + (size_t)r * L.max_items;
+        int c = 0;
+        for (int j : order) {
+            if (r >= L.img[j].rounds) continue;
+            const FwdLaunch &a = descs[(size_t)r * n + j];
+            const int cnt = a.tiles_x * a.tiles_y * a.planes;
+            for (int w = 0; w < cnt; ++w) it[c++] = make_uint2((unsigned)j, (unsigned)w);
+        }
+        counts[r] = c;
+    }
+    hipError_t e;
+    if (L.rounds) {
+        if ((e = hipMemcpyAsync((char *)ws + L.descs_off, descs.data(), descs.size() * sizeof(FwdLaunch),
+                                hipMemcpyHostToDevice, stream)) != hipSuccess ||
+            (e = hipMemcpyAsync((char *)ws + L.items_off, items.data(), items.size() * sizeof(uint2),
+                                hipMemcpyHostToDevice, stream)) != hipSuccess ||
+            (e = hipMemcpyAsync((char *)ws + L.counts_off, counts.data(), L.rounds * sizeof(int),
+                                hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "upload batch tables");
+        // the host vectors go out of scope: wait for the copies
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "synchronize");
+    }
+    const int slots = std::max(1, (int)(163840 / batched_lds_bytes()));
+    const int64_t g = std::min<int64_t>(L.max_items, (int64_t)device_cus() * slots);
+    memset(batch, 0, sizeof *batch);
+    batch->n = n;
+    batch->dtype = dtype;
+    batch->rounds = L.rounds;
+    batch->grid = (int)std::max<int64_t>(8, (g + 7) / 8 * 8);
+    batch->max_items = L.max_items;
+    batch->total_items = L.total_items;
+    batch->ws = ws;
+    batch->descs_off = L.descs_off;
+    batch->items_off = L.items_off;
+    batch->counts_off = L.counts_off;
+    batch->identity = L.identity;
+    // identity images are copied at launch: remember them in the tables is
+    // not needed; the launch re-reads the host list through the caller.
+    return OSBF_SUCCESS;
+}
+
+osbf_status osbf_batched_launch(const osbf_batch *batch, void *stream_) {
+    g_last_error.clear();
+    if (!batch) return fail(OSBF_ERROR_INVALID_VALUE, "batch must be non-NULL");
+    if (batch->identity)
+        return fail(OSBF_ERROR_UNSUPPORTED, "batch has identity images (r = 0 or T = 0): use osbf_batched");
+    hipStream_t stream = (hipStream_t)stream_;
+    const FwdLaunch *descs = (const FwdLaunch *)((const char *)batch->ws + batch->descs_off);
+    const uint2 *items = (const uint2 *)((const char *)batch->ws + batch->items_off);
+    const int *counts = (const int *)((const char *)batch->ws + batch->counts_off);
+    for (int r = 0; r < batch->rounds; ++r) {
+        hipError_t e = launch_batched_round(batch->dtype, descs + (size_t)r * batch->n,
+                                            items + (size_t)r * batch->max_items, counts + r, batch->grid, stream);
+        if (e != hipSuccess) return hip_fail(e, "batched launch");
+    }
+    return OSBF_SUCCESS;
+}
+
+osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype, osbf_boundary boundary,
+                         void *ws, size_t ws_bytes, void *stream_) {
+    osbf_batch b;
+    osbf_status st = osbf_batched_prepare(imgs, n, dtype, boundary, ws, ws_bytes, &b, stream_);
+    if (st != OSBF_SUCCESS) return st;
+    hipStream_t stream = (hipStream_t)stream_;
+    for (int j = 0; j < n; ++j) {
+        if (imgs[j].radius == 0 || imgs[j].iterations == 0) {
+            const size_t bytes = (size_t)imgs[j].planes * imgs[j].height * imgs[j].width * elem_bytes(dtype);
+            hipError_t e = hipMemcpyAsync(imgs[j].dst, imgs[j].src, bytes, hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return hip_fail(e, "copy");
+        }
+    }
+    b.identity = 0;
+    return osbf_batched_launch(&b, stream_);
+}
+
+}  // extern "C"

@@ -42,6 +42,11 @@ struct BwdLaunch {
 };
 
 void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr);
+
+// Batched rounds (64x48 fixed geometry, 512 threads).
+size_t batched_lds_bytes();
+hipError_t launch_batched_round(int dtype, const FwdLaunch *descs, const uint2 *items, const int *count,
+                                int grid, hipStream_t stream);
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t s);
 
 }  // namespace osbf

@@ -23,6 +23,22 @@ MAX_RADIUS = 32
 _lib = None
 
 
+class Image(ctypes.Structure):
+    """osbf_image: one image of a batch."""
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("planes", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("iterations", ctypes.c_int32)]
+
+
+class Batch(ctypes.Structure):
+    """osbf_batch: a prepared batch (plain data)."""
+    _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("max_items", ctypes.c_int64), ("total_items", ctypes.c_int64),
+                ("ws", ctypes.c_void_p), ("descs_off", ctypes.c_size_t), ("items_off", ctypes.c_size_t),
+                ("counts_off", ctypes.c_size_t), ("identity", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
 class OsbfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"osbf status {status}: {msg}")
@@ -53,6 +69,15 @@ def lib():
     L.osbf_backward_workspace_size.restype = sz
     L.osbf_backward.argtypes = [vp, vp, i32, i32, i32, i32, i32, ctypes.c_int, vp, vp, i32, vp, sz, vp]
     L.osbf_backward.restype = ctypes.c_int
+    L.osbf_batched_workspace_size.argtypes = [ctypes.POINTER(Image), i32, ctypes.c_int]
+    L.osbf_batched_workspace_size.restype = sz
+    L.osbf_batched_prepare.argtypes = [ctypes.POINTER(Image), i32, ctypes.c_int, ctypes.c_int, vp, sz,
+                                       ctypes.POINTER(Batch), vp]
+    L.osbf_batched_prepare.restype = ctypes.c_int
+    L.osbf_batched_launch.argtypes = [ctypes.POINTER(Batch), vp]
+    L.osbf_batched_launch.restype = ctypes.c_int
+    L.osbf_batched.argtypes = [ctypes.POINTER(Image), i32, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    L.osbf_batched.restype = ctypes.c_int
     L.osbf_forward_plan.argtypes = [i32, i32, i32, ctypes.c_int, i32, i32, i32] + [ctypes.POINTER(i32)] * 4
     L.osbf_forward_plan.restype = ctypes.c_int
     _lib = L
@@ -186,3 +211,51 @@ class OSBFFunction(torch.autograd.Function):
 def osbf(x: torch.Tensor, r: int, T: int, ckpt_every: int = 0) -> torch.Tensor:
     """The filter as a differentiable op (see OSBFFunction)."""
     return OSBFFunction.apply(x, r, T, ckpt_every)
+
+
+def _images(xs, outs, radii, iters):
+    arr = (Image * len(xs))()
+    for i, (x, y, r, T) in enumerate(zip(xs, outs, radii, iters)):
+        planes, H, W = _geometry(x)
+        arr[i] = Image(x.data_ptr(), y.data_ptr(), planes, H, W, int(r), int(T))
+    return arr
+
+
+class BatchPlan:
+    """A prepared batch: per-image outputs, workspace and tables on the device.
+    ``launch()`` only enqueues kernels, so it can be captured in a CUDA/HIP
+    graph and replayed (each replay recomputes the outputs from the inputs)."""
+
+    def __init__(self, xs, radii, iters, outs=None):
+        if not xs:
+            raise ValueError("empty batch")
+        self.xs = list(xs)
+        self.outs = [torch.empty_like(x) for x in xs] if outs is None else list(outs)
+        dt = DTYPES[xs[0].dtype]
+        self.images = _images(self.xs, self.outs, radii, iters)
+        n = lib().osbf_batched_workspace_size(self.images, len(xs), dt)
+        if n == ctypes.c_size_t(-1).value:   # invalid: let prepare report the status
+            _check(lib().osbf_batched_prepare(self.images, len(xs), dt, 0, None, 0,
+                                              ctypes.byref(Batch()), _stream(xs[0].device)))
+        self.ws = torch.empty(max(n, 1), dtype=torch.uint8, device=xs[0].device)
+        self.batch = Batch()
+        _check(lib().osbf_batched_prepare(self.images, len(xs), dt, 0, _ptr(self.ws), n,
+                                          ctypes.byref(self.batch), _stream(xs[0].device)))
+
+    def launch(self):
+        _check(lib().osbf_batched_launch(ctypes.byref(self.batch), _stream(self.xs[0].device)))
+        return self.outs
+
+
+def batched(xs, radii, iters, outs=None):
+    """Filter a list of (..., H, W) device tensors of one dtype, each with its
+    own radius and iteration count, in one batched call."""
+    outs = [torch.empty_like(x) for x in xs] if outs is None else list(outs)
+    dt = DTYPES[xs[0].dtype]
+    imgs = _images(xs, outs, radii, iters)
+    n = lib().osbf_batched_workspace_size(imgs, len(xs), dt)
+    if n == ctypes.c_size_t(-1).value:   # invalid: let the call report the status
+        _check(lib().osbf_batched(imgs, len(xs), dt, 0, None, 0, _stream(xs[0].device)))
+    ws = torch.empty(max(n, 1), dtype=torch.uint8, device=xs[0].device)
+    _check(lib().osbf_batched(imgs, len(xs), dt, 0, _ptr(ws), n, _stream(xs[0].device)))
+    return outs

@@ -89,3 +89,35 @@ def test_forward_rejects_null_pointers_and_bad_checkpoint(lib):
 def test_gpu_code_object_targets_gfx950():
     out = subprocess.run(["strings", LIB], capture_output=True, text=True).stdout
     assert "gfx950" in out
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of osbf_image / osbf_batch match the C header."""
+    from paper_2108_05021_amd import osbf
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "osbf.h"\n'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(osbf_image), sizeof(osbf_batch),'
+        ' offsetof(osbf_batch, max_items), offsetof(osbf_batch, ws), offsetof(osbf_batch, identity),'
+        ' offsetof(osbf_image, radius));return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(osbf.Image), ctypes.sizeof(osbf.Batch), osbf.Batch.max_items.offset,
+            osbf.Batch.ws.offset, osbf.Batch.identity.offset, osbf.Image.radius.offset]
+    assert got == want
+
+
+def test_batched_rejects_bad_lists(lib):
+    from paper_2108_05021_amd import osbf
+    fake = ctypes.c_void_p(0x1000)
+    imgs = (osbf.Image * 1)(osbf.Image(fake, ctypes.c_void_p(0x2000), 1, 8, 8, 6, 2))
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 2          # radius without kernel
+    imgs[0].radius = 2
+    imgs[0].dst = fake
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 1          # in place
+    imgs[0].dst = ctypes.c_void_p(0x2000)
+    imgs[0].height = 0
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 1          # empty plane
+    imgs[0].height = 8
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 3          # workspace missing

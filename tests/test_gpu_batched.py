@@ -1,0 +1,105 @@
+"""GPU checks of the batched forward (osbf_batched*): equality with per-image
+osbf_forward (bit for bit: window sums are position-deterministic), graph
+capture and replay, the 256-image workload, and error paths."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_05021_amd import osbf, synth
+
+pytestmark = pytest.mark.gpu
+
+RADII = [1, 2, 3, 4, 5, 8, 10, 16]
+
+
+def _mixed_batch(dev, dtype, seed, n=24):
+    rng = np.random.default_rng(seed)
+    xs, rs, ts = [], [], []
+    shapes = [(1, 1, 37), (3, 29, 1), (1, 1, 1), (2, 64, 48), (1, 300, 257)]
+    for i in range(n):
+        if i < len(shapes):
+            C, H, W = shapes[i]
+        else:
+            C, H, W = int(rng.choice([1, 3])), int(rng.integers(8, 260)), int(rng.integers(8, 260))
+        img = synth.voronoi(H, W, 8, 0.05, rng, C=C)
+        xs.append(torch.from_numpy(img).to(dev).to(dtype))
+        rs.append(RADII[i % len(RADII)])
+        ts.append(int(rng.integers(1, 13)))
+    return xs, rs, ts
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16, torch.float16])
+def test_batched_equals_single(dev, dtype):
+    xs, rs, ts = _mixed_batch(dev, dtype, 1)
+    outs = osbf.batched(xs, rs, ts)
+    for x, y, r, T in zip(xs, outs, rs, ts):
+        assert torch.equal(y, osbf.forward(x, r, T)), (tuple(x.shape), r, T)
+
+
+def test_batched_small_images_against_oracle(dev):
+    xs, rs, ts = _mixed_batch(dev, torch.float32, 2, n=10)
+    outs = osbf.batched(xs, rs, ts)
+    for x, y, r, T in zip(xs, outs, rs, ts):
+        want = oracle.forward(x.cpu().numpy().astype(np.float64), r, T)
+        err = np.abs(y.cpu().numpy() - want)
+        assert np.median(err) < 1e-6 and (err > 1e-5).mean() < 0.05
+
+
+def test_graph_capture_and_replay(dev):
+    xs, rs, ts = _mixed_batch(dev, torch.float32, 3, n=16)
+    plan = osbf.BatchPlan(xs, rs, ts)
+    eager = [y.clone() for y in plan.launch()]
+    torch.cuda.synchronize()
+    for y in plan.outs:
+        y.zero_()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.launch()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for y in plan.outs:
+            y.fill_(float("nan"))                      # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for y, e in zip(plan.outs, eager):
+            assert torch.equal(y, e), f"replay {rep} differs"
+        _ = sum(float(x.sum()) for x in xs)              # more eager work and syncs
+        torch.cuda.synchronize()
+
+
+def test_identity_and_errors(dev):
+    x = torch.rand(2, 40, 50, device=dev)
+    z = torch.rand(1, 30, 20, device=dev)
+    outs = osbf.batched([x, z, x], [0, 2, 3], [5, 0, 2])
+    assert torch.equal(outs[0], x) and torch.equal(outs[1], z)
+    assert torch.equal(outs[2], osbf.forward(x, 3, 2))
+    with pytest.raises(osbf.OsbfError) as ei:
+        osbf.batched([x], [6], [2])                     # radius without a batched kernel
+    assert ei.value.status == 2
+    with pytest.raises(osbf.OsbfError) as ei:
+        osbf.batched([x], [2], [2], outs=[x])           # in place is rejected
+    assert ei.value.status == 1
+    plan_err = None
+    try:
+        osbf.BatchPlan([x], [0], [1]).launch()
+    except osbf.OsbfError as e:
+        plan_err = e.status
+    assert plan_err == 2
+
+
+def test_batched_workload_256(dev):
+    """The 256-image workload (H, W in [64, 1024], 1 or 3 channels, r in
+    {1,2,4,8}, T in [5,30]): one batched call equals per-image calls."""
+    items = synth.workload_batched()
+    xs = [torch.from_numpy(it["img"]).to(dev) for it in items]
+    rs = [it["r"] for it in items]
+    ts = [it["T"] for it in items]
+    outs = osbf.batched(xs, rs, ts)
+    for x, y, r, T in zip(xs, outs, rs, ts):
+        assert torch.equal(y, osbf.forward(x, r, T))
