@@ -7,9 +7,18 @@ r in {2, 5, 10}.  The metric is megapixel-iterations per second
 (H*W*C*T summed over the three radii, per second) and its share of the HBM
 roofline at 8 bytes per pixel-sweep (read and write one FP32 iterate).
 
+The other forms of the filter are reported under "forms", each next to the
+plain FP32 forward on the same workload:
+  batched   256 images, H, W in [64, 1024], 1 or 3 channels, r in {1,2,4,8},
+            T in [5, 30]; one prepared batch replayed as a HIP graph
+  bf16/f16  1x8192x8192 stored as BF16 / FP16, r=16, T=20, with max/mean
+            error against the FP64 oracle on crops (storage-only and total)
+  fwd_bwd   32x3x512x512, r=3, T=10, loss sum(W*U): forward with uint8
+            selection maps + backward, and with a checkpoint every 5 sweeps
+
 Prints one JSON line (see the repository's benchmark contract).  Inputs are
-resident in HBM before the timed region; the timed region is K steps between
-two device synchronisations.
+resident in HBM before every timed region; each timed region is bracketed by
+device synchronisations.
 """
 from __future__ import annotations
 
@@ -73,13 +82,147 @@ def cpu_baseline(img, sweeps: int = 2):
                       f"({total_t:.1f} s wall)"}
 
 
+def _timed(fn, reps, warmup=2):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def form_batched(reps):
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    items = synth.workload_batched()
+    xs = [torch.from_numpy(it["img"]).cuda() for it in items]
+    rs = [it["r"] for it in items]
+    ts = [it["T"] for it in items]
+    pxit = sum(x.numel() * T for x, T in zip(xs, ts))
+    plan = osbf.BatchPlan(xs, rs, ts)
+    plan.launch()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            plan.launch()
+    torch.cuda.current_stream().wait_stream(st)
+    t_graph = _timed(g.replay, reps)
+    t_eager = _timed(plan.launch, reps)
+    outs = [torch.empty_like(x) for x in xs]
+
+    def single():
+        for x, y, r, T in zip(xs, outs, rs, ts):
+            osbf.forward(x, r, T, out=y)
+    t_single = _timed(single, max(1, reps // 2), warmup=1)
+    return {"workload": "256 images, H,W in [64,1024], C in {1,3}, Voronoi K=16 + N(0,0.05^2), "
+                        "r in {1,2,4,8}, T in [5,30], f32",
+            "mpix_it": round(pxit / 1e6, 1), "rounds": plan.batch.rounds, "grid": plan.batch.grid,
+            "graph_ms": round(t_graph * 1e3, 3), "mpix_it_s": round(pxit / t_graph / 1e6, 1),
+            "eager_launch_mpix_it_s": round(pxit / t_eager / 1e6, 1),
+            "plain_fp32_forward_per_image_mpix_it_s": round(pxit / t_single / 1e6, 1),
+            "vs_plain_fwd": round(t_single / t_graph, 3)}
+
+
+def _crop_errors(full_in, gpu_out, r, T, crops, size=32):
+    """max/mean |GPU - oracle| on crops; the oracle runs on the crop grown by
+    r*T (clipped to the image), whose centre is exact."""
+    import numpy as np
+    import oracle
+    H, W = full_in.shape
+    m = r * T
+    errs = []
+    for (y0, x0) in crops:
+        ya, yb = max(0, y0 - m), min(H, y0 + size + m)
+        xa, xb = max(0, x0 - m), min(W, x0 + size + m)
+        want = oracle.forward(full_in[ya:yb, xa:xb].astype(np.float64), r, T)
+        got = gpu_out[y0:y0 + size, x0:x0 + size].astype(np.float64)
+        errs.append(np.abs(got - want[y0 - ya:y0 - ya + size, x0 - xa:x0 - xa + size]))
+    e = np.concatenate([v.ravel() for v in errs])
+    return float(e.max()), float(e.mean())
+
+
+def form_precision(reps, errors=True):
+    import numpy as np
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    r, T = 16, 20
+    img = synth.workload_precision()[0]
+    x32 = torch.from_numpy(img).cuda()[None]
+    pxit = x32.numel() * T
+    t32 = _timed(lambda: osbf.forward(x32, r, T), reps)
+    out = {"workload": "1x8192x8192 Voronoi K=256 + N(0,0.02^2), r=16, T=20",
+           "plain_fp32_forward_mpix_it_s": round(pxit / t32 / 1e6, 1)}
+    crops = [(0, 0), (4000, 4100), (8192 - 32, 8192 - 32)]
+    y32 = osbf.forward(x32, r, T)[0].cpu().numpy() if errors else None
+    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        xs = x32.to(dt)
+        t = _timed(lambda: osbf.forward(xs, r, T), reps)
+        d = {"mpix_it_s": round(pxit / t / 1e6, 1), "vs_plain_fwd": round(t32 / t, 3)}
+        if errors:
+            y = osbf.forward(xs, r, T)[0].float().cpu().numpy()
+            cast_in = xs[0].float().cpu().numpy()
+            d["storage_only_err_max"], d["storage_only_err_mean"] = _crop_errors(cast_in, y, r, T, crops)
+            d["total_err_max"], d["total_err_mean"] = _crop_errors(img, y, r, T, crops)
+            d["err_sample"] = "3 crops of 32x32 (corner, centre, far corner)"
+        out[name] = d
+    if errors:
+        e = _crop_errors(img, y32, r, T, crops)
+        out["f32_err_max"], out["f32_err_mean"] = e
+    return out
+
+
+def form_fwd_bwd(reps):
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    r, T = 3, 10
+    x_np, w_np = synth.workload_grad()
+    x = torch.from_numpy(x_np).cuda()
+    w = torch.from_numpy(w_np).cuda()
+    pxit = x.numel() * T
+    t_fwd = _timed(lambda: osbf.forward(x, r, T), reps)
+
+    def maps():
+        y, sel = osbf.forward(x, r, T, return_sel=True)
+        return osbf.backward(w, r, T, sel=sel)
+
+    def ckpt():
+        y, ck = osbf.forward(x, r, T, ckpt_every=5)
+        return osbf.backward(w, r, T, ckpt=ck, ck=5)
+    t_maps = _timed(maps, reps)
+    t_ck = _timed(ckpt, reps)
+    return {"workload": "32x3x512x512 Voronoi K=64 + N(0,0.05^2), r=3, T=10, loss sum(W*U), W~N(0,1)",
+            "plain_fp32_forward_mpix_it_s": round(pxit / t_fwd / 1e6, 1),
+            "maps_u8": {"mpix_it_s": round(pxit / t_maps / 1e6, 1), "vs_plain_fwd": round(t_fwd / t_maps, 3),
+                        "map_bytes": T * x.numel()},
+            "ckpt_every_5": {"mpix_it_s": round(pxit / t_ck / 1e6, 1), "vs_plain_fwd": round(t_fwd / t_ck, 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched/bf16/f16/fwd+bwd forms")
+    ap.add_argument("--no-errors", action="store_true", help="skip the oracle error crops of the bf16/f16 form")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy 5 times (for scaling HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the filter's multi-GPU "
               "sharding is a design note, not built.", file=sys.stderr)
@@ -164,6 +307,13 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(img)
+    if not args.no_forms:
+        del x, out, ws
+        torch.cuda.empty_cache()
+        reps = 5
+        line["forms"] = {"batched": form_batched(reps),
+                         "precision": form_precision(reps, errors=not args.no_errors),
+                         "fwd_bwd": form_fwd_bwd(reps)}
     print(json.dumps(line), flush=True)
 
 

@@ -106,12 +106,13 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 }
 
 // Measured defaults for the compiled radii (3x2048x2048 FP32, T=30 on
-// MI355X): 512-thread 64x48 regions up to r=8, 1024-thread 128x64 regions
-// for larger radii; fusion pays off for r <= 3.
+// MI355X, plan sweep over geometries and fusion depths): 512-thread 64-wide
+// regions up to r=10, the 1024-thread 128x64 region for r=16; fusion pays
+// off for r <= 3.
 struct TunedShape { int r, geom, k; };
-const TunedShape kTuned[] = {{1, GEOM_64x48, 3}, {2, GEOM_64x48, 3}, {3, GEOM_64x48, 2},
-                             {4, GEOM_64x48, 1}, {5, GEOM_64x48, 1}, {8, GEOM_64x48, 1},
-                             {10, GEOM_128x64, 1}, {16, GEOM_128x64, 1}};
+const TunedShape kTuned[] = {{1, GEOM_64x48, 3}, {2, GEOM_64x48, 2}, {3, GEOM_64x48, 2},
+                             {4, GEOM_64x60, 1}, {5, GEOM_64x60, 1}, {8, GEOM_64x48, 1},
+                             {10, GEOM_64x60, 1}, {16, GEOM_128x64, 1}};
 
 // OSBF_PLAN="geom,k" forces a plan (tests and tuning): geom 0 is the generic
 // kernel (region chosen by cost), 1.. the fixed geometries (enum Geom).

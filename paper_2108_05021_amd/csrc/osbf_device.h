@@ -69,12 +69,17 @@ __device__ __forceinline__ Pick select8(const float d[8]) {
         duel(a0, i0, a2, i2);
         return Pick{a0, i0};
     } else {
-        a0 = fabsf(d[1]) < fabsf(a0) ? d[1] : a0;
-        a1 = fabsf(d[3]) < fabsf(a1) ? d[3] : a1;
-        a2 = fabsf(d[5]) < fabsf(a2) ? d[5] : a2;
-        a3 = fabsf(d[7]) < fabsf(a3) ? d[7] : a3;
-        a0 = fabsf(a1) < fabsf(a0) ? a1 : a0;
-        a2 = fabsf(a3) < fabsf(a2) ? a3 : a2;
+        // the four first-round comparisons are independent; evaluating them
+        // before any select lets them share the issue slots of the selects
+        const bool c0 = fabsf(d[1]) < fabsf(a0), c1 = fabsf(d[3]) < fabsf(a1);
+        const bool c2 = fabsf(d[5]) < fabsf(a2), c3 = fabsf(d[7]) < fabsf(a3);
+        a0 = c0 ? d[1] : a0;
+        a1 = c1 ? d[3] : a1;
+        a2 = c2 ? d[5] : a2;
+        a3 = c3 ? d[7] : a3;
+        const bool c4 = fabsf(a1) < fabsf(a0), c5 = fabsf(a3) < fabsf(a2);
+        a0 = c4 ? a1 : a0;
+        a2 = c5 ? a3 : a2;
         a0 = fabsf(a2) < fabsf(a0) ? a2 : a0;
         return Pick{a0, 0};
     }

@@ -399,12 +399,23 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
     const bool interior = (X0 - ext >= 0) && (Y0 - ext >= 0) && (X0 + TW + ext <= W) &&
                           (Y0 + TH + ext <= H);
 
-    {   // clamped load of tile + halo
+    {   // clamped load of tile + halo: every row load of a thread is issued
+        // before the first wait, then written to LDS
+        constexpr int NL = (RH + NY - 1) / NY;
         const int x = ox + lx;
         const int y0 = max(0, oy), y1 = min(H, Y0 + TH + ext);
         if (x >= 0 && x < W && lx < TW + 2 * ext) {
-            for (int y = y0 + ly; y < y1; y += NY)
-                P[(y - oy) * PITCH + lx] = S::load(src, (size_t)y * W + x);
+            float v[NL];
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int y = y0 + ly + i * NY;
+                v[i] = y < y1 ? S::load(src, (size_t)y * W + x) : 0.f;
+            }
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int y = y0 + ly + i * NY;
+                if (y < y1) P[(y - oy) * PITCH + lx] = v[i];
+            }
         }
     }
     __syncthreads();
@@ -437,7 +448,7 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
                 uint8_t *sel = SEL ? a.sel + (size_t)j * a.sel_stride + plane_off : nullptr;
                 typename S::T *dst = (typename S::T *)a.dst + plane_off;
                 const bool core_x = x >= X0 && x < X0 + TW;
-                for (int y = ya + ly; y < yb; y += NY) {
+                auto update = [&](int y, float &u, int &idx) {
                     const int o = (y - oy) * PITCH + lx;
                     constexpr int RD = R * PITCH;
                     const float c = P[o];
@@ -457,12 +468,26 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
                     d[6] = fmaf(f2r1, ne, nc);
                     d[7] = fmaf(f2r1, nw, nc);
                     const Pick pk = select8<SEL>(d);
-                    const float u = S::round(fmaf(pk.d, invN, c));
-                    if (SEL && core_x && y >= Y0 && y < Y0 + TH) sel[(size_t)y * W + x] = (uint8_t)pk.idx;
-                    if (last)
+                    u = S::round(fmaf(pk.d, invN, c));
+                    idx = pk.idx;
+                    return o;
+                };
+                if (last) {
+                    for (int y = ya + ly; y < yb; y += NY) {
+                        float u;
+                        int idx;
+                        update(y, u, idx);
+                        if (SEL && core_x && y >= Y0 && y < Y0 + TH) sel[(size_t)y * W + x] = (uint8_t)idx;
                         dst[(size_t)y * W + x] = S::pack(u);
-                    else
+                    }
+                } else {
+                    for (int y = ya + ly; y < yb; y += NY) {
+                        float u;
+                        int idx;
+                        const int o = update(y, u, idx);
+                        if (SEL && core_x && y >= Y0 && y < Y0 + TH) sel[(size_t)y * W + x] = (uint8_t)idx;
                         P[o] = u;
+                    }
                 }
             }
             if (!last) __syncthreads();
