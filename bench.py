@@ -15,6 +15,8 @@ plain FP32 forward on the same workload:
             error against the FP64 oracle on crops (storage-only and total)
   fwd_bwd   32x3x512x512, r=3, T=10, loss sum(W*U): forward with uint8
             selection maps + backward, and with a checkpoint every 5 sweeps
+  variants  the bench workload through the fast approximation (Alg. 3) and
+            the classical box filter, the paper's two timing comparisons
 
 Prints one JSON line (see the repository's benchmark contract).  Inputs are
 resident in HBM before every timed region; each timed region is bracketed by
@@ -203,6 +205,23 @@ def form_fwd_bwd(reps):
             "ckpt_every_5": {"mpix_it_s": round(pxit / t_ck / 1e6, 1), "vs_plain_fwd": round(t_fwd / t_ck, 3)}}
 
 
+def form_variants(reps):
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    x = torch.from_numpy(synth.workload_rgb()).cuda()
+    pxit = x.numel() * T_SWEEPS * len(RADII)
+    t = {}
+    for name, fn in (("exact", osbf.forward), ("fast", osbf.forward_fast), ("box", osbf.box_forward)):
+        t[name] = _timed(lambda: [fn(x, r, T_SWEEPS) for r in RADII], reps)
+    return {"workload": "3x2048x2048 f32, r in {2,5,10}, T=30 (the bench workload)",
+            "exact_mpix_it_s": round(pxit / t["exact"] / 1e6, 1),
+            "fast_mpix_it_s": round(pxit / t["fast"] / 1e6, 1),
+            "box_mpix_it_s": round(pxit / t["box"] / 1e6, 1),
+            "fast_time_over_exact": round(t["fast"] / t["exact"], 3),
+            "exact_time_over_box": round(t["exact"] / t["box"], 3),
+            "paper_context": "fast/exact ~0.6 and exact/box ~8 (MATLAB) or ~6 (C++) on a laptop CPU, r unstated"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,7 +332,8 @@ def main():
         reps = 5
         line["forms"] = {"batched": form_batched(reps),
                          "precision": form_precision(reps, errors=not args.no_errors),
-                         "fwd_bwd": form_fwd_bwd(reps)}
+                         "fwd_bwd": form_fwd_bwd(reps),
+                         "variants": form_variants(reps)}
     print(json.dumps(line), flush=True)
 
 

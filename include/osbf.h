@@ -112,6 +112,30 @@ osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t hei
                          void *ckpt, int32_t ck, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * osbf_forward_fast -- T sweeps of the fast approximation of Alg. 3
+ * (Sec. III-F): only the north-west quadrant mean field is computed per
+ * sweep; the four quadrant candidates are its shifts by {0, r}, and each half
+ * window is replaced by the average of its two quadrants (eq:app), so pixels
+ * on the shared centre row or column count twice.  The candidate closest to
+ * the pixel's value is taken, ties in osbf_window order.  Arguments,
+ * boundary, workspace (osbf_forward_workspace_size) and in-place rules as
+ * for osbf_forward; no selection maps or checkpoints.
+ */
+osbf_status osbf_forward_fast(const void *src, void *dst, int32_t planes, int32_t height,
+                              int32_t width, osbf_dtype dtype, int32_t radius, int32_t iterations,
+                              osbf_boundary boundary, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * osbf_box_forward -- T sweeps of the classical box filter, the mean over the
+ * full (2r+1) x (2r+1) window (the baseline the paper times its filter
+ * against, Sec. III-G, Table I), with the same boundary, layout, workspace
+ * and in-place rules as osbf_forward.
+ */
+osbf_status osbf_box_forward(const void *src, void *dst, int32_t planes, int32_t height,
+                             int32_t width, osbf_dtype dtype, int32_t radius, int32_t iterations,
+                             osbf_boundary boundary, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Workspace bytes osbf_backward needs: one FP32 plane set for the gradient
  * ping-pong, plus (checkpoint mode, ck > 0) two FP32 plane sets and
  * min(ck, T) uint8 maps for recomputing one segment.  (size_t)-1 if invalid.

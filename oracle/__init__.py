@@ -64,6 +64,12 @@ def _load():
     lib.oracle_adjoint_scatter.restype = None
     lib.oracle_backward.argtypes = [d, d, d, u8, ci, ci, ci, ci, ci, ci]
     lib.oracle_backward.restype = ci
+    lib.oracle_fast_sweep.argtypes = [d, d, u8, d, ci, ci, ci, ci]
+    lib.oracle_fast_sweep.restype = None
+    lib.oracle_fast_forward.argtypes = [d, d, ci, ci, ci, ci, ci, ci]
+    lib.oracle_fast_forward.restype = ci
+    lib.oracle_box_forward.argtypes = [d, d, ci, ci, ci, ci, ci]
+    lib.oracle_box_forward.restype = ci
     lib.oracle_window_extent.argtypes = [ci, ci, ci, ci] + [ctypes.POINTER(ci)] * 4
     lib.oracle_window_extent.restype = None
     _lib = lib
@@ -182,3 +188,37 @@ def backward(x, grad_out, r: int, T: int, *, return_sel: bool = False, nthreads:
         raise ValueError("oracle_backward failed")
     gin = gin.reshape(shape)
     return (gin, sel) if return_sel else gin
+
+
+def fast_sweep(u, r: int, *, nthreads: int = 0):
+    """One sweep of the fast approximation (Alg. 3) on one plane: returns
+    (next, sel [H,W] uint8, candidates [H,W,8])."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    H, W = u.shape
+    out = np.empty_like(u)
+    sel = np.empty((H, W), np.uint8)
+    cand = np.empty((H, W, 8), np.float64)
+    _load().oracle_fast_sweep(_pd(u), _pd(out), _pu8(sel), _pd(cand), H, W, r, nthreads)
+    return out, sel, cand
+
+
+def fast_forward(x, r: int, T: int, *, nthreads: int = 0):
+    """T sweeps of the fast approximation (Alg. 3), clamp boundary."""
+    shape = np.shape(x)
+    a = _planes(x)
+    P, H, W = a.shape
+    out = np.empty_like(a)
+    if _load().oracle_fast_forward(_pd(a), _pd(out), P, H, W, r, T, nthreads) != 0:
+        raise ValueError("oracle_fast_forward failed")
+    return out.reshape(shape)
+
+
+def box_forward(x, r: int, T: int):
+    """T sweeps of the classical (2r+1)^2 box filter, clamp boundary."""
+    shape = np.shape(x)
+    a = _planes(x)
+    P, H, W = a.shape
+    out = np.empty_like(a)
+    if _load().oracle_box_forward(_pd(a), _pd(out), P, H, W, r, T) != 0:
+        raise ValueError("oracle_box_forward failed")
+    return out.reshape(shape)

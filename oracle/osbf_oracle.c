@@ -309,3 +309,121 @@ int oracle_backward(const double *in, const double *grad_out, double *grad_in,
     free(sel); free(a); free(b);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Fast approximation (Alg. 3, Sec. III-F).
+ *
+ * Readings: the one field computed per sweep is the mean of the north-west
+ * ("left up", y pointing down) quadrant ending at the pixel,
+ *   Qm(x,y) = mean of P over [x-r, x] x [y-r, y];
+ * the four quadrant candidates are its shifts by {0, r} in x and y
+ * (NW = Qm(x,y), NE = Qm(x+r,y), SW = Qm(x,y+r), SE = Qm(x+r,y+r)), and each
+ * half window is replaced by the average of its two quadrants (eq:app):
+ *   R ~ (NE+SE)/2, L ~ (NW+SW)/2, D ~ (SW+SE)/2, U ~ (NW+NE)/2.
+ * The new value is the candidate closest to the current one, ties in the
+ * order R, L, D, U, SE, SW, NE, NW (as for the exact filter); the printed
+ * update U + d(x+u,y+v) is read as "take the selected candidate".
+ * ------------------------------------------------------------------------ */
+
+/* Mean of P over [x-r, x] x [y-r, y] with clamped coordinates. */
+static double nw_mean_clamp(const double *u, int H, int W, int x, int y, int r)
+{
+    double s = 0.0;
+    for (int yy = y - r; yy <= y; ++yy)
+        for (int xx = x - r; xx <= x; ++xx)
+            s += u[(size_t)clampi(yy, 0, H - 1) * W + clampi(xx, 0, W - 1)];
+    return s / ((double)(r + 1) * (r + 1));
+}
+
+/* One sweep of the fast approximation; cand nullable [H][W][8]. */
+void oracle_fast_sweep(const double *u, double *out, uint8_t *sel, double *cand,
+                       int H, int W, int r, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            const double nw = nw_mean_clamp(u, H, W, x, y, r);
+            const double ne = nw_mean_clamp(u, H, W, x + r, y, r);
+            const double sw = nw_mean_clamp(u, H, W, x, y + r, r);
+            const double se = nw_mean_clamp(u, H, W, x + r, y + r, r);
+            double a[O_NWIN];
+            a[O_R] = 0.5 * (ne + se);
+            a[O_L] = 0.5 * (nw + sw);
+            a[O_D] = 0.5 * (sw + se);
+            a[O_U] = 0.5 * (nw + ne);
+            a[O_SE] = se;
+            a[O_SW] = sw;
+            a[O_NE] = ne;
+            a[O_NW] = nw;
+            const size_t p = (size_t)y * W + x;
+            const double c = u[p];
+            int m = 0;
+            double best = 0.0;
+            for (int i = 0; i < O_NWIN; ++i) {
+                const double e = fabs(a[i] - c);
+                if (i == 0 || e < best) { best = e; m = i; }
+                if (cand) cand[p * O_NWIN + i] = a[i];
+            }
+            out[p] = a[m];
+            if (sel) sel[p] = (uint8_t)m;
+        }
+    }
+    (void)nthreads;
+}
+
+/* T sweeps of the fast approximation on `planes` planes (clamp boundary). */
+int oracle_fast_forward(const double *in, double *out, int planes, int H, int W, int r, int T,
+                        int nthreads)
+{
+    if (planes < 0 || H < 0 || W < 0 || r < 0 || T < 0) return -1;
+    size_t n = (size_t)H * W;
+    if (n == 0 || planes == 0) return 0;
+    double *a = (double *)malloc(n * sizeof(double));
+    double *b = (double *)malloc(n * sizeof(double));
+    if (!a || !b) { free(a); free(b); return -1; }
+    for (int pl = 0; pl < planes; ++pl) {
+        memcpy(a, in + (size_t)pl * n, n * sizeof(double));
+        for (int t = 0; t < T; ++t) {
+            oracle_fast_sweep(a, b, NULL, NULL, H, W, r, nthreads);
+            double *tmp = a; a = b; b = tmp;
+        }
+        memcpy(out + (size_t)pl * n, a, n * sizeof(double));
+    }
+    free(a); free(b);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Classical box filter (the paper's timing baseline, Table I): the mean of
+ * P over the full window [x-r, x+r] x [y-r, y+r], clamp boundary, T sweeps.
+ * ------------------------------------------------------------------------ */
+int oracle_box_forward(const double *in, double *out, int planes, int H, int W, int r, int T)
+{
+    if (planes < 0 || H < 0 || W < 0 || r < 0 || T < 0) return -1;
+    size_t n = (size_t)H * W;
+    if (n == 0 || planes == 0) return 0;
+    double *a = (double *)malloc(n * sizeof(double));
+    double *b = (double *)malloc(n * sizeof(double));
+    if (!a || !b) { free(a); free(b); return -1; }
+    const double cnt = (double)(2 * r + 1) * (2 * r + 1);
+    for (int pl = 0; pl < planes; ++pl) {
+        memcpy(a, in + (size_t)pl * n, n * sizeof(double));
+        for (int t = 0; t < T; ++t) {
+            for (int y = 0; y < H; ++y)
+                for (int x = 0; x < W; ++x) {
+                    double s = 0.0;
+                    for (int yy = y - r; yy <= y + r; ++yy)
+                        for (int xx = x - r; xx <= x + r; ++xx)
+                            s += a[(size_t)clampi(yy, 0, H - 1) * W + clampi(xx, 0, W - 1)];
+                    b[(size_t)y * W + x] = s / cnt;
+                }
+            double *tmp = a; a = b; b = tmp;
+        }
+        memcpy(out + (size_t)pl * n, a, n * sizeof(double));
+    }
+    free(a); free(b);
+    return 0;
+}

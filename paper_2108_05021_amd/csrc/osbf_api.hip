@@ -179,7 +179,8 @@ std::vector<Launch> make_launches(int T, int ck, int k) {
 // the grid stays within 2^31 workgroups.  `sel_t0` is the map of sweep t0,
 // plane 0 (nullable); consecutive sweeps' maps are plane_set apart.
 hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, uint8_t *sel_t0,
-                           int planes, int H, int W, int r, osbf_dtype dtype, hipStream_t stream) {
+                           int planes, int H, int W, int r, osbf_dtype dtype, hipStream_t stream,
+                           int mode = 0) {
     const size_t plane_set = (size_t)planes * H * W;
     const int tiles_x = (W + plan.tw - 1) / plan.tw, tiles_y = (H + plan.th - 1) / plan.th;
     const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)tiles_x * tiles_y)));
@@ -200,7 +201,7 @@ hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, u
             fwd_lds_layout(plan.tw, plan.th, r, k, &a.pitch, &a.arr);
         else
             a.pitch = plan.pitch, a.arr = plan.arr;
-        hipError_t e = launch_forward((int)dtype, a, stream);
+        hipError_t e = mode ? launch_forward_mode(mode, (int)dtype, a, stream) : launch_forward((int)dtype, a, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -262,10 +263,13 @@ size_t osbf_forward_workspace_size(int32_t planes, int32_t H, int32_t W, osbf_dt
     return (size_t)planes * H * W * elem_bytes(dtype);
 }
 
-osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
+}  // extern "C"
+
+namespace {
+osbf_status forward_impl(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
                          osbf_dtype dtype, int32_t r, int32_t T, osbf_boundary boundary,
                          uint8_t *sel, void *ckpt, int32_t ck, void *ws, size_t ws_bytes,
-                         void *stream_) {
+                         void *stream_, int mode) {
     g_last_error.clear();
     osbf_status st = check_sizes(planes, H, W, dtype, r, T);
     if (st != OSBF_SUCCESS) return st;
@@ -313,11 +317,37 @@ osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t H, 
                 return hip_fail(e, "copy checkpoint");
         }
         uint8_t *sel_t0 = sel ? sel + (size_t)launches[i].t0 * plane_set : nullptr;
-        if ((e = enqueue_forward(plan, launches[i].k, cur, out, sel_t0, planes, H, W, r, dtype, stream)) != hipSuccess)
+        if ((e = enqueue_forward(plan, launches[i].k, cur, out, sel_t0, planes, H, W, r, dtype, stream,
+                                 mode)) != hipSuccess)
             return hip_fail(e, "forward launch");
         cur = out;
     }
     return OSBF_SUCCESS;
+}
+}  // namespace
+
+extern "C" {
+
+osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
+                         osbf_dtype dtype, int32_t r, int32_t T, osbf_boundary boundary,
+                         uint8_t *sel, void *ckpt, int32_t ck, void *ws, size_t ws_bytes,
+                         void *stream) {
+    return forward_impl(src, dst, planes, H, W, dtype, r, T, boundary, sel, ckpt, ck, ws, ws_bytes,
+                        stream, 0);
+}
+
+osbf_status osbf_forward_fast(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
+                              osbf_dtype dtype, int32_t r, int32_t T, osbf_boundary boundary,
+                              void *ws, size_t ws_bytes, void *stream) {
+    return forward_impl(src, dst, planes, H, W, dtype, r, T, boundary, nullptr, nullptr, 0, ws,
+                        ws_bytes, stream, 1);
+}
+
+osbf_status osbf_box_forward(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
+                             osbf_dtype dtype, int32_t r, int32_t T, osbf_boundary boundary,
+                             void *ws, size_t ws_bytes, void *stream) {
+    return forward_impl(src, dst, planes, H, W, dtype, r, T, boundary, nullptr, nullptr, 0, ws,
+                        ws_bytes, stream, 2);
 }
 
 size_t osbf_backward_workspace_size(int32_t planes, int32_t H, int32_t W, int32_t r, int32_t T,

@@ -15,6 +15,7 @@ template <int DT> struct Storage;
 
 template <> struct Storage<DT_F32> {
     using T = float;
+    static __device__ __forceinline__ float cvt(T v) { return v; }
     static __device__ __forceinline__ float load(const T *p, size_t i) { return p[i]; }
     static __device__ __forceinline__ T pack(float v) { return v; }
     static __device__ __forceinline__ float round(float v) { return v; }
@@ -22,6 +23,7 @@ template <> struct Storage<DT_F32> {
 
 template <> struct Storage<DT_F16> {
     using T = _Float16;
+    static __device__ __forceinline__ float cvt(T v) { return (float)v; }
     static __device__ __forceinline__ float load(const T *p, size_t i) { return (float)p[i]; }
     static __device__ __forceinline__ T pack(float v) { return (T)v; }
     static __device__ __forceinline__ float round(float v) { return (float)(T)v; }
@@ -29,9 +31,8 @@ template <> struct Storage<DT_F16> {
 
 template <> struct Storage<DT_BF16> {
     using T = uint16_t;
-    static __device__ __forceinline__ float load(const T *p, size_t i) {
-        return __uint_as_float(((uint32_t)p[i]) << 16);
-    }
+    static __device__ __forceinline__ float cvt(T v) { return __uint_as_float(((uint32_t)v) << 16); }
+    static __device__ __forceinline__ float load(const T *p, size_t i) { return cvt(p[i]); }
     // Round to nearest even on the upper 16 bits (inputs are finite).
     static __device__ __forceinline__ T pack(float v) {
         uint32_t u = __float_as_uint(v);

@@ -35,6 +35,54 @@
 
 namespace osbf {
 
+enum : int { MODE_EXACT = 0, MODE_FAST = 1, MODE_BOX = 2 };
+
+// Sum of the full (2r+1)^2 box from the same fields: the four quadrants
+// cover it with the centre row segments [x-r,x] and [x,x+r] and the centre
+// column segments counted twice and the centre pixel four times.
+__device__ __forceinline__ float box_sum(float nw, float ne, float sw, float se, float hl, float hr,
+                                         float vu, float vd, float c) {
+    return ((nw + ne) + (sw + se)) - ((hl + hr) + (vu + vd)) + c;
+}
+
+// Signed scaled differences of the exact filter (Alg. 2): N times
+// (mean_i - c) for the windows R, L, D, U, SE, SW, NE, NW, from the four
+// quadrant sums, the row sums H at x and x+r and the column sums V at y and
+// y+r (each half is two quadrants minus their shared row or column).
+__device__ __forceinline__ void exact_distances(float d[8], float nw, float ne, float sw, float se,
+                                                float hl, float hr, float vu, float vd, float c,
+                                                float fr1, float f2r1, float N) {
+    const float sR = ne + se - hr;
+    const float sL = nw + sw - hl;
+    const float sD = sw + se - vd;
+    const float sU = nw + ne - vu;
+    const float nc = -N * c;
+    d[0] = fmaf(fr1, sR, nc);
+    d[1] = fmaf(fr1, sL, nc);
+    d[2] = fmaf(fr1, sD, nc);
+    d[3] = fmaf(fr1, sU, nc);
+    d[4] = fmaf(f2r1, se, nc);
+    d[5] = fmaf(f2r1, sw, nc);
+    d[6] = fmaf(f2r1, ne, nc);
+    d[7] = fmaf(f2r1, nw, nc);
+}
+
+// Signed scaled differences of the fast approximation (Alg. 3): 2 (r+1)^2
+// times (candidate - c), where each half is the average of its two
+// quadrants (eq:app) and the quadrants are the quadrant means themselves.
+__device__ __forceinline__ void fast_distances(float d[8], float nw, float ne, float sw, float se,
+                                               float c, float fr1) {
+    const float nc = -2.f * fr1 * fr1 * c;
+    d[0] = (ne + se) + nc;
+    d[1] = (nw + sw) + nc;
+    d[2] = (sw + se) + nc;
+    d[3] = (nw + ne) + nc;
+    d[4] = fmaf(2.f, se, nc);
+    d[5] = fmaf(2.f, sw, nc);
+    d[6] = fmaf(2.f, ne, nc);
+    d[7] = fmaf(2.f, nw, nc);
+}
+
 template <bool CL>
 __device__ __forceinline__ int cidx(int v, int hi) {
     return CL ? min(max(v, 0), hi) : v;
@@ -79,7 +127,7 @@ __device__ __forceinline__ void phase_v(const float *Pi, float *Vi, int pitch, i
 
 // Phase B: Q on columns [xa, xend), rows [ya, yq); H on the same columns,
 // rows [ya, yh).  Blocks of r columns anchored at multiples of r.
-template <int R, bool CL>
+template <int R, bool CL, int MODE = 0>
 __device__ __forceinline__ void phase_qh(const float *Pi, const float *Vi, float *Qi, float *Hi,
                                          int pitch, int r, int W, int xa, int xend, int ya, int yq,
                                          int yh, int tx, int ty) {
@@ -90,7 +138,7 @@ __device__ __forceinline__ void phase_qh(const float *Pi, const float *Vi, float
         const int x1 = min(x0 + r, xend);
         for (int rr = tx; rr < nrow; rr += 64) {
             const int y = ya + rr;
-            const bool doH = y < yh;
+            const bool doH = MODE != MODE_FAST && y < yh;
             const float *vr = Vi + y * pitch;
             const float *pr = Pi + y * pitch;
             float *qr = Qi + y * pitch;
@@ -142,7 +190,10 @@ __device__ __forceinline__ void phase_qh(const float *Pi, const float *Vi, float
 }
 
 // k fused sweeps on one tile.  `lds` holds four arrays of a.arr floats.
-template <int DT, int R, bool SEL>
+// MODE: MODE_EXACT (Alg. 2), MODE_FAST (the approximation of Alg. 3: quadrant
+// means only, halves as pair averages, no H field) or MODE_BOX (the classical
+// (2r+1)^2 box mean the paper times its filter against).
+template <int DT, int R, bool SEL, int MODE = 0>
 __device__ __forceinline__ void fwd_tile(const FwdLaunch &a, int tile_x, int tile_y, int plane,
                                          float *lds) {
     using S = Storage<DT>;
@@ -180,6 +231,7 @@ __device__ __forceinline__ void fwd_tile(const FwdLaunch &a, int tile_x, int til
     const float fr1 = (float)(r + 1), f2r1 = (float)(2 * r + 1);
     const float N = fr1 * fr1 * f2r1;
     const float invN = 1.0f / N;
+    const float inv_box = 1.0f / (f2r1 * f2r1);
 
     for (int j = 0; j < k; ++j) {
         const int e = (k - 1 - j) * r;
@@ -192,9 +244,9 @@ __device__ __forceinline__ void fwd_tile(const FwdLaunch &a, int tile_x, int til
             phase_v<R, true>(Pi, Vi, pitch, r, H, max(0, xa - r), min(W, xb + r), ya, yb + r, tx, ty);
         __syncthreads();
         if (interior)
-            phase_qh<R, false>(Pi, Vi, Qi, Hi, pitch, r, W, xa, xb + r, ya, yb + r, yb, tx, ty);
+            phase_qh<R, false, MODE>(Pi, Vi, Qi, Hi, pitch, r, W, xa, xb + r, ya, yb + r, yb, tx, ty);
         else
-            phase_qh<R, true>(Pi, Vi, Qi, Hi, pitch, r, W, xa, xb + r, ya, yb + r, yb, tx, ty);
+            phase_qh<R, true, MODE>(Pi, Vi, Qi, Hi, pitch, r, W, xa, xb + r, ya, yb + r, yb, tx, ty);
         __syncthreads();
 
         // Phase C: selection and update on [xa, xb) x [ya, yb).
@@ -207,22 +259,19 @@ __device__ __forceinline__ void fwd_tile(const FwdLaunch &a, int tile_x, int til
                 const int o = y * pitch + x, od = o + rp;
                 const float c = Pi[o];
                 const float nw = Qi[o], ne = Qi[o + r], sw = Qi[od], se = Qi[od + r];
-                const float sR = ne + se - Hi[o + r];
-                const float sL = nw + sw - Hi[o];
-                const float sD = sw + se - Vi[od];
-                const float sU = nw + ne - Vi[o];
-                const float nc = -N * c;
-                float d[8];
-                d[0] = fmaf(fr1, sR, nc);
-                d[1] = fmaf(fr1, sL, nc);
-                d[2] = fmaf(fr1, sD, nc);
-                d[3] = fmaf(fr1, sU, nc);
-                d[4] = fmaf(f2r1, se, nc);
-                d[5] = fmaf(f2r1, sw, nc);
-                d[6] = fmaf(f2r1, ne, nc);
-                d[7] = fmaf(f2r1, nw, nc);
-                const Pick p = select8<SEL>(d);
-                const float u = S::round(fmaf(p.d, invN, c));
+                float u;
+                Pick p{0.f, 0};
+                if constexpr (MODE == MODE_BOX) {
+                    u = S::round(box_sum(nw, ne, sw, se, Hi[o], Hi[o + r], Vi[o], Vi[od], c) * inv_box);
+                } else {
+                    float d[8];
+                    if constexpr (MODE == MODE_FAST)
+                        fast_distances(d, nw, ne, sw, se, c, fr1);
+                    else
+                        exact_distances(d, nw, ne, sw, se, Hi[o], Hi[o + r], Vi[o], Vi[od], c, fr1, f2r1, N);
+                    p = select8<SEL>(d);
+                    u = S::round(fmaf(p.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c));
+                }
                 if (SEL) {
                     const bool core = (x >= X0) && (x < X0 + TW) && (y >= Y0) && (y < Y0 + TH);
                     if (core) sel[(size_t)y * W + x] = (uint8_t)p.idx;
@@ -246,14 +295,14 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return xcd * q + min(xcd, rem) + idx;
 }
 
-template <int DT, int R, bool SEL>
+template <int DT, int R, bool SEL, int MODE = 0>
 __global__ __launch_bounds__(256) void fwd_tile_kernel(FwdLaunch a) {
     extern __shared__ float lds[];
     const int ntiles = a.tiles_x * a.tiles_y;
     const int total = ntiles * a.planes;
     const int t = xcd_remap(blockIdx.x, total);
     const int plane = t / ntiles, tile = t - plane * ntiles;
-    fwd_tile<DT, R, SEL>(a, tile % a.tiles_x, tile / a.tiles_x, plane, lds);
+    fwd_tile<DT, R, SEL, MODE>(a, tile % a.tiles_x, tile / a.tiles_x, plane, lds);
 }
 
 // Phase A of the fixed-geometry kernel: V on columns [max(0,xa-R),
@@ -304,7 +353,7 @@ __device__ __forceinline__ void fixed_phase_v(const float *P, float *V, int lx, 
 
 // Phase B of the fixed-geometry kernel: Q on columns [xa, xb+R), rows
 // [ya, yb+R); H on the same columns, rows [ya, yb).  One lane per region row.
-template <int R, int RW, int RH, int NT, bool CL>
+template <int R, int RW, int RH, int NT, bool CL, int MODE = 0>
 __device__ __forceinline__ void fixed_phase_qh(const float *P, const float *V, float *Q, float *Hs,
                                                int lr, int lb, int ox, int oy, int W, int xa,
                                                int xb, int ya, int yb) {
@@ -312,7 +361,7 @@ __device__ __forceinline__ void fixed_phase_qh(const float *P, const float *V, f
     constexpr int NB = NT / 64;  // lane groups over column blocks
     const int y = oy + lr;
     if (lr >= RH || y < ya || y >= yb + R) return;
-    const bool doH = y < yb;
+    const bool doH = MODE != MODE_FAST && y < yb;
     const int xend = xb + R;
     const int nblk = (xend - xa + R - 1) / R;
     for (int b = lb; b < nblk; b += NB) {
@@ -371,7 +420,7 @@ __device__ __forceinline__ void fixed_phase_qh(const float *P, const float *V, f
 // immediate offset from one base address; one wave spans a region row.  The
 // arithmetic is the same sequence of FP32 operations as fwd_tile (same block
 // anchors, same summation order), so both kernels give identical bits.
-template <int DT, int R, int RW, int RH, int NT, bool SEL>
+template <int DT, int R, int RW, int RH, int NT, bool SEL, int MODE = 0>
 __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int tile_y, int plane,
                                           float *lds) {
     using S = Storage<DT>;
@@ -400,21 +449,22 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
                           (Y0 + TH + ext <= H);
 
     {   // clamped load of tile + halo: every row load of a thread is issued
-        // before the first wait, then written to LDS
+        // (from an in-bounds, clamped row) before the first wait; values are
+        // converted and written to LDS afterwards
         constexpr int NL = (RH + NY - 1) / NY;
         const int x = ox + lx;
         const int y0 = max(0, oy), y1 = min(H, Y0 + TH + ext);
         if (x >= 0 && x < W && lx < TW + 2 * ext) {
-            float v[NL];
+            typename S::T raw[NL];
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
-                const int y = y0 + ly + i * NY;
-                v[i] = y < y1 ? S::load(src, (size_t)y * W + x) : 0.f;
+                const int y = min(y0 + ly + i * NY, y1 - 1);
+                raw[i] = src[(size_t)y * W + x];
             }
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
                 const int y = y0 + ly + i * NY;
-                if (y < y1) P[(y - oy) * PITCH + lx] = v[i];
+                if (y < y1) P[(y - oy) * PITCH + lx] = S::cvt(raw[i]);
             }
         }
     }
@@ -423,6 +473,7 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
     constexpr float fr1 = (float)(R + 1), f2r1 = (float)(2 * R + 1);
     constexpr float N = fr1 * fr1 * f2r1;
     const float invN = 1.0f / N;
+    const float inv_box = 1.0f / (f2r1 * f2r1);
 
     for (int j = 0; j < k; ++j) {
         const int e = (k - 1 - j) * R;
@@ -432,11 +483,11 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
         if (interior) {
             fixed_phase_v<R, RW, RH, NT, false>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
             __syncthreads();
-            fixed_phase_qh<R, RW, RH, NT, false>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
+            fixed_phase_qh<R, RW, RH, NT, false, MODE>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
         } else {
             fixed_phase_v<R, RW, RH, NT, true>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
             __syncthreads();
-            fixed_phase_qh<R, RW, RH, NT, true>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
+            fixed_phase_qh<R, RW, RH, NT, true, MODE>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
         }
         __syncthreads();
 
@@ -453,23 +504,19 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
                     constexpr int RD = R * PITCH;
                     const float c = P[o];
                     const float nw = Q[o], ne = Q[o + R], sw = Q[o + RD], se = Q[o + RD + R];
-                    const float sR = ne + se - Hs[o + R];
-                    const float sL = nw + sw - Hs[o];
-                    const float sD = sw + se - V[o + RD];
-                    const float sU = nw + ne - V[o];
-                    const float nc = -N * c;
-                    float d[8];
-                    d[0] = fmaf(fr1, sR, nc);
-                    d[1] = fmaf(fr1, sL, nc);
-                    d[2] = fmaf(fr1, sD, nc);
-                    d[3] = fmaf(fr1, sU, nc);
-                    d[4] = fmaf(f2r1, se, nc);
-                    d[5] = fmaf(f2r1, sw, nc);
-                    d[6] = fmaf(f2r1, ne, nc);
-                    d[7] = fmaf(f2r1, nw, nc);
-                    const Pick pk = select8<SEL>(d);
-                    u = S::round(fmaf(pk.d, invN, c));
-                    idx = pk.idx;
+                    if constexpr (MODE == MODE_BOX) {
+                        u = S::round(box_sum(nw, ne, sw, se, Hs[o], Hs[o + R], V[o], V[o + RD], c) * inv_box);
+                        idx = 0;
+                    } else {
+                        float d[8];
+                        if constexpr (MODE == MODE_FAST)
+                            fast_distances(d, nw, ne, sw, se, c, fr1);
+                        else
+                            exact_distances(d, nw, ne, sw, se, Hs[o], Hs[o + R], V[o], V[o + RD], c, fr1, f2r1, N);
+                        const Pick pk = select8<SEL>(d);
+                        u = S::round(fmaf(pk.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c));
+                        idx = pk.idx;
+                    }
                     return o;
                 };
                 if (last) {
@@ -495,14 +542,14 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
     }
 }
 
-template <int DT, int R, int RW, int RH, int NT, bool SEL>
+template <int DT, int R, int RW, int RH, int NT, bool SEL, int MODE = 0>
 __global__ __launch_bounds__(NT) void fwd_fixed_kernel(FwdLaunch a) {
     extern __shared__ float lds[];
     const int ntiles = a.tiles_x * a.tiles_y;
     const int total = ntiles * a.planes;
     const int t = xcd_remap(blockIdx.x, total);
     const int plane = t / ntiles, tile = t - plane * ntiles;
-    fwd_fixed<DT, R, RW, RH, NT, SEL>(a, tile % a.tiles_x, tile / a.tiles_x, plane, lds);
+    fwd_fixed<DT, R, RW, RH, NT, SEL, MODE>(a, tile % a.tiles_x, tile / a.tiles_x, plane, lds);
 }
 
 }  // namespace osbf

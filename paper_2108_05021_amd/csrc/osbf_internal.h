@@ -30,6 +30,8 @@ bool fixed_radius(int r);
 bool fwd_tile_shape(int RW, int RH, int r, int k, int *tw, int *th);
 void fwd_lds_layout(int tw, int th, int r, int k, int *pitch, int *arr);
 hipError_t launch_forward(int dtype, const FwdLaunch &a, hipStream_t s);
+// mode 1: fast approximation (Alg. 3); mode 2: classical box filter.
+hipError_t launch_forward_mode(int mode, int dtype, const FwdLaunch &a, hipStream_t s);
 
 // One launch of the adjoint kernel: G = A_t^T Gnext for every plane.
 struct BwdLaunch {

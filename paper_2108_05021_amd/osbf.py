@@ -65,6 +65,10 @@ def lib():
     L.osbf_forward.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int,
                                vp, vp, i32, vp, sz, vp]
     L.osbf_forward.restype = ctypes.c_int
+    L.osbf_forward_fast.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int, vp, sz, vp]
+    L.osbf_forward_fast.restype = ctypes.c_int
+    L.osbf_box_forward.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int, vp, sz, vp]
+    L.osbf_box_forward.restype = ctypes.c_int
     L.osbf_backward_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32]
     L.osbf_backward_workspace_size.restype = sz
     L.osbf_backward.argtypes = [vp, vp, i32, i32, i32, i32, i32, ctypes.c_int, vp, vp, i32, vp, sz, vp]
@@ -259,3 +263,23 @@ def batched(xs, radii, iters, outs=None):
     ws = torch.empty(max(n, 1), dtype=torch.uint8, device=xs[0].device)
     _check(lib().osbf_batched(imgs, len(xs), dt, 0, _ptr(ws), n, _stream(xs[0].device)))
     return outs
+
+
+def _mode_forward(fn, x, r, T, out):
+    planes, H, W = _geometry(x)
+    y = torch.empty_like(x) if out is None else out
+    nbytes = forward_workspace_size(planes, H, W, x.dtype, r, T)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=x.device) if nbytes else None
+    _check(fn(_ptr(x), _ptr(y), planes, H, W, DTYPES[x.dtype], r, T, 0, _ptr(ws),
+              0 if ws is None else ws.numel(), _stream(x.device)))
+    return y
+
+
+def forward_fast(x: torch.Tensor, r: int, T: int, *, out: torch.Tensor | None = None):
+    """T sweeps of the fast approximation (Alg. 3) on a (..., H, W) tensor."""
+    return _mode_forward(lib().osbf_forward_fast, x, r, T, out)
+
+
+def box_forward(x: torch.Tensor, r: int, T: int, *, out: torch.Tensor | None = None):
+    """T sweeps of the classical (2r+1)^2 box filter (replicate boundary)."""
+    return _mode_forward(lib().osbf_box_forward, x, r, T, out)

@@ -146,3 +146,21 @@ def replay_check_planes(u0, u_gpu, sels, r, tol=1e-5, max_outliers=0):
         flips += f
     assert tot_bad <= max_outliers
     return tot_bad, worst, flips
+
+
+def check_fast_sweep(u_in, u_out, r: int, tol: float = 1e-5):
+    """Teacher-forced check of one sweep of the fast approximation (Alg. 3):
+    the GPU value must be the oracle's value of a near-minimal candidate
+    (distances scaled by 2 (r+1)^2, tau as for the exact filter with that
+    scale).  Returns the number of value-changing flips."""
+    u_in = np.asarray(u_in, np.float64)
+    u_out = np.asarray(u_out, np.float64)
+    out_o, sel_o, cand = oracle.fast_sweep(u_in, r)
+    scale = 2.0 * (r + 1) ** 2
+    err = np.abs(cand - u_in[..., None]) * scale
+    emin = err.min(axis=2)
+    t = 2.0 ** -19 * scale * (1.0 + float(np.abs(u_in).max()))
+    near = err - emin[..., None] <= t
+    dev = np.where(near, np.abs(u_out[..., None] - cand), np.inf).min(axis=2)
+    assert dev.max() <= tol, f"fast: value matches no near-minimal candidate (off by {dev.max():.3e})"
+    return int((np.abs(u_out - out_o) > tol).sum())

@@ -27,7 +27,8 @@ def _golden():
         return json.load(f)["cases"]
 
 
-@pytest.mark.parametrize("case", _golden(), ids=lambda c: c["name"])
+@pytest.mark.parametrize("case", [c for c in _golden() if c.get("method", "exact") == "exact"],
+                         ids=lambda c: c["name"])
 def test_hand_worked(case):
     img = np.array(case["image"], np.float64)
     r, T = case["r"], case["T"]
@@ -369,3 +370,87 @@ def test_backward_matches_finite_differences(seed, r, T):
         assert fd == pytest.approx(grad[yy, xx], rel=1e-6, abs=1e-8)
         checked += 1
     assert checked >= 3
+
+
+# ------------------------------------------- fast approximation (Alg. 3)
+
+@pytest.mark.parametrize("case", [c for c in _golden() if c.get("method") == "fast"], ids=lambda c: c["name"])
+def test_fast_hand_worked(case):
+    u = np.array(case["image"], np.float64)
+    for t in range(case["T"]):
+        u, sel, _ = oracle.fast_sweep(u, case["r"])
+        np.testing.assert_array_equal(u, np.array(case["out_per_sweep"][t], np.float64))
+        np.testing.assert_array_equal(sel, np.array(case["sel_per_sweep"][t]))
+    np.testing.assert_array_equal(oracle.fast_forward(np.array(case["image"], float), case["r"], case["T"]), u)
+
+
+@pytest.mark.parametrize("seed,r", [(90, 1), (91, 2), (92, 4)])
+def test_fast_candidates_are_exact_quadrants_and_pair_averages(seed, r):
+    """The fast filter's quadrant candidates are the exact filter's quadrant
+    means, and each half candidate is the mean of its two quadrants (eq:app);
+    the exact oracle computes these from its own direct window sums."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((11, 13))
+    _, _, cand = oracle.fast_sweep(u, r)
+    _, _, _, means = oracle.sweep(u, r, return_means=True)
+    np.testing.assert_allclose(cand[..., 4:], means[..., 4:], rtol=0, atol=1e-14)
+    SE, SW, NE, NW = (means[..., i] for i in (4, 5, 6, 7))
+    want_halves = np.stack([(NE + SE) / 2, (NW + SW) / 2, (SW + SE) / 2, (NW + NE) / 2], axis=-1)
+    np.testing.assert_allclose(cand[..., :4], want_halves, rtol=0, atol=1e-14)
+
+
+def test_fast_invariants():
+    img = np.full((9, 10), 0.625)
+    np.testing.assert_array_equal(oracle.fast_forward(img, 2, 4), img)
+    yy, xx = np.mgrid[0:15, 0:16]
+    for a, b, c in [(1, 0, 5), (1, 1, 9), (2, -1, 3)]:
+        step = np.where(a * xx + b * yy >= c, 0.75, 0.125)
+        np.testing.assert_array_equal(oracle.fast_forward(step, 2, 5), step)
+    rng = np.random.default_rng(93)
+    x = rng.random((2, 14, 12))
+    out = oracle.fast_forward(x, 3, 3)
+    for p in range(2):
+        assert out[p].min() >= x[p].min() - 1e-12 and out[p].max() <= x[p].max() + 1e-12
+
+
+def _fast_1d(v, r, T):
+    """Exact-rational 1D fast filter: candidates right mean, left mean and
+    their average, first minimum in that order (R, L, D)."""
+    v = [Fraction(t) for t in v]
+    n = len(v)
+    for _ in range(T):
+        at = lambda i: v[min(max(i, 0), n - 1)]
+        nxt = []
+        for x in range(n):
+            right = sum(at(x + j) for j in range(r + 1)) / (r + 1)
+            left = sum(at(x - j) for j in range(r + 1)) / (r + 1)
+            best = None
+            for cval in (right, left, (left + right) / 2):
+                dd = abs(cval - v[x])
+                if best is None or dd < best[0]:
+                    best = (dd, cval)
+            nxt.append(best[1])
+        v = nxt
+    return np.array([float(t) for t in v])
+
+
+@pytest.mark.parametrize("r,T", [(1, 1), (2, 1), (1, 3), (3, 2)])
+def test_fast_rows_constant_reduce_to_1d(r, T):
+    row = _row(60 + r, 21, T)
+    out = oracle.fast_forward(np.tile(row, (5, 1)), r, T)
+    np.testing.assert_allclose(out, np.tile(_fast_1d(row, r, T), (5, 1)), atol=1e-13)
+
+
+# ------------------------------------------------------- box filter baseline
+
+@pytest.mark.parametrize("r,T", [(1, 1), (2, 3), (4, 2)])
+def test_box_matches_scipy_uniform_filter(r, T):
+    """The classical box filter with replicate boundary is scipy's
+    uniform_filter with mode='nearest', applied T times."""
+    from scipy.ndimage import uniform_filter
+    rng = np.random.default_rng(100 + r)
+    img = rng.random((17, 23))
+    want = img.copy()
+    for _ in range(T):
+        want = uniform_filter(want, size=2 * r + 1, mode="nearest")
+    np.testing.assert_allclose(oracle.box_forward(img, r, T), want, rtol=0, atol=1e-13)
