@@ -55,7 +55,7 @@ extern "C" {
 typedef enum {
     OSBF_SUCCESS = 0,
     OSBF_ERROR_INVALID_VALUE = 1,   /* null pointer, bad size, out-of-range enum */
-    OSBF_ERROR_UNSUPPORTED = 2,     /* valid request this build cannot serve */
+    OSBF_ERROR_UNSUPPORTED = 2,     /* valid request the library has no kernel for */
     OSBF_ERROR_WORKSPACE = 3,       /* workspace missing or too small */
     OSBF_ERROR_HIP = 4,             /* a HIP runtime call or launch failed */
     OSBF_ERROR_TIMEOUT = 5          /* a device-side bounded wait expired */
