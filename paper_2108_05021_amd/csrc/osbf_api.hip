@@ -210,13 +210,24 @@ hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, u
 // Tile of the adjoint kernel: the largest multiple of r whose 2r-grown
 // region fits the smallest of 64/80/96/128 pixels that leaves a tile, within
 // the device's LDS.
-bool adjoint_tile(int r, int *tw, int *th, int *pitch, int *arr) {
+// Adjoint tiling: the fixed-geometry kernel for its radii (OSBF_ADJOINT=
+// generic forces the generic kernel), else the smallest square region of the
+// generic kernel that fits the device's LDS.
+bool adjoint_tile(int r, BwdLaunch *b) {
+    const char *env = getenv("OSBF_ADJOINT");
+    const bool force_generic = env && strcmp(env, "generic") == 0;
+    b->fixed = 0;
+    if (!force_generic && adjoint_fixed_tile(r, &b->tw, &b->th)) {
+        b->fixed = 1;
+        b->pitch = b->arr = 0;
+        return true;
+    }
     for (int reg : {64, 80, 96, 128}) {
         const int t = ((reg - 4 * r) / r) * r;
         if (t < std::max(r, 4)) continue;
-        bwd_lds_layout(t, t, r, pitch, arr);
-        if ((size_t)5 * (*arr) * sizeof(float) <= lds_limit()) {
-            *tw = *th = t;
+        bwd_lds_layout(t, t, r, &b->pitch, &b->arr);
+        if ((size_t)5 * b->arr * sizeof(float) <= lds_limit()) {
+            b->tw = b->th = t;
             return true;
         }
     }
@@ -388,7 +399,7 @@ osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes,
         return fail(OSBF_ERROR_WORKSPACE, "workspace of %zu bytes required, got %zu", need, ws ? ws_bytes : 0);
 
     BwdLaunch b;
-    if (!adjoint_tile(r, &b.tw, &b.th, &b.pitch, &b.arr))
+    if (!adjoint_tile(r, &b))
         return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
     b.H = H; b.W = W; b.r = r;
     b.tiles_x = (W + b.tw - 1) / b.tw;

@@ -195,6 +195,225 @@ __global__ __launch_bounds__(256) void adjoint_kernel(BwdLaunch a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fixed-geometry adjoint for the common radii.  The LDS region is RW x RH
+// pixels (the tile grown by 2R on every side) with a compile-time pitch; the
+// selection lives in a byte array.  The vertical pass gives each lane one
+// region column and reads a block's 3R rows into registers once; the
+// horizontal pass spreads (row, column block) pairs over all lanes.  The
+// FP32 operations and their order are those of adjoint_kernel, so both
+// kernels give the same bits.
+template <int R, int RW, int RH, int NT>
+__global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
+    extern __shared__ float lds[];
+    constexpr int PITCH = RW + 1, ARR = RH * PITCH, NY = NT / RW;
+    static_assert(RW == 64 && NT % 64 == 0, "one wave per region row");
+    float *const GV = lds;                 // gv, later Gpad
+    float *const HL = lds + ARR;
+    float *const HR = lds + 2 * ARR;
+    float *const VF = lds + 3 * ARR;
+    uint8_t *const SL = (uint8_t *)(lds + 4 * ARR);
+    const int tid = threadIdx.x, lx = tid % RW;
+    const int ly = __builtin_amdgcn_readfirstlane(tid / RW);
+    const int H = a.H, W = a.W, TW = a.tw, TH = a.th;
+    const int ntiles = a.tiles_x * a.tiles_y;
+    const int t = xcd_remap(blockIdx.x, ntiles * a.planes);
+    const int plane = t / ntiles, tile = t - plane * ntiles;
+    const int X0 = (tile % a.tiles_x) * TW, Y0 = (tile / a.tiles_x) * TH;
+    const int ox = X0 - 2 * R, oy = Y0 - 2 * R;  // image coords of LDS (0,0)
+    const size_t plane_off = (size_t)plane * H * W;
+    const float *gn = a.gnext + plane_off;
+    const uint8_t *sl = a.sel + plane_off;
+
+    // q region (tile grown by R beyond every image edge it touches) and the
+    // F region it reads (q region grown by R)
+    const int qx0 = X0 == 0 ? -R : X0, qx1 = X0 + TW >= W ? W + R : X0 + TW;
+    const int qy0 = Y0 == 0 ? -R : Y0, qy1 = Y0 + TH >= H ? H + R : Y0 + TH;
+    const int gx0 = qx0 - R, gx1 = qx1 + R, gy0 = qy0 - R, gy1 = qy1 + R;
+    const float inv_h = 1.0f / (float)((R + 1) * (2 * R + 1));
+    const float inv_q = 1.0f / (float)((R + 1) * (R + 1));
+    const int x = ox + lx;
+    const bool xcol = x >= gx0 && x < gx1;
+
+    // Phase 0: gv and selection on the F region, zero outside the image.
+    // Every load of a lane is issued (clamped into the image) before the
+    // first wait.
+    if (xcol) {
+        constexpr int NL = (RH + NY - 1) / NY;
+        const bool xin = x >= 0 && x < W;
+        const int xc = min(max(x, 0), W - 1);
+        float graw[NL];
+        uint8_t sraw[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int y = min(max(min(gy0 + ly + i * NY, gy1 - 1), 0), H - 1);
+            graw[i] = gn[(size_t)y * W + xc];
+            sraw[i] = sl[(size_t)y * W + xc];
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int y = gy0 + ly + i * NY;
+            if (y < gy1) {
+                const int o = (y - oy) * PITCH + lx;
+                const bool in = xin && y >= 0 && y < H;
+                const int s = sraw[i];
+                GV[o] = in ? graw[i] * (s >= 4 ? inv_q : inv_h) : 0.f;
+                SL[o] = in ? sraw[i] : 0;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase A: per column of [qx0 - R, qx1 + R), VL+VF, VR+VF and VF on rows
+    // [qy0, qy1) in blocks of R rows anchored at multiples of R.
+    if (xcol) {
+        const int nblk = (qy1 - qy0 + R - 1) / R;
+        for (int b = ly; b < nblk; b += NY) {
+            const int y0 = qy0 + b * R;
+            const bool full = y0 + R <= qy1;
+            float g[3 * R];
+            int s[3 * R];
+#pragma unroll
+            for (int i = 0; i < 3 * R; ++i) {  // rows y0-R .. y0+2R-1
+                const int o = (min(y0 - R + i, gy1 - 1) - oy) * PITCH + lx;
+                g[i] = GV[o];
+                s[i] = SL[o];
+            }
+            float u1 = pick(M_C1, s[0], g[0]), u3 = pick(M_C3, s[0], g[0]), ud = pick(M_FD, s[0], g[0]);
+#pragma unroll
+            for (int i = 1; i <= R; ++i) {
+                u1 += pick(M_C1, s[i], g[i]);
+                u3 += pick(M_C3, s[i], g[i]);
+                ud += pick(M_FD, s[i], g[i]);
+            }
+            float d2 = pick(M_C2, s[R], g[R]), d4 = pick(M_C4, s[R], g[R]), du = pick(M_FU, s[R], g[R]);
+#pragma unroll
+            for (int i = R + 1; i <= 2 * R; ++i) {
+                d2 += pick(M_C2, s[i], g[i]);
+                d4 += pick(M_C4, s[i], g[i]);
+                du += pick(M_FU, s[i], g[i]);
+            }
+            auto emit = [&](int tt) {
+                const int i = R + tt;
+                const float vf = ud + du;
+                const float vl = u1 + d2 - pick(M_FR, s[i], g[i]);
+                const float vr = u3 + d4 - pick(M_FL, s[i], g[i]);
+                const int o = (y0 + tt - oy) * PITCH + lx;
+                HL[o] = vl + vf;
+                HR[o] = vr + vf;
+                VF[o] = vf;
+            };
+            emit(0);
+#pragma unroll
+            for (int tt = 1; tt < R; ++tt) {
+                if (full || y0 + tt < qy1) {
+                    const int n = R + tt, od = tt - 1, n2 = 2 * R + tt, od2 = R + tt - 1;
+                    u1 += pick(M_C1, s[n], g[n]) - pick(M_C1, s[od], g[od]);
+                    u3 += pick(M_C3, s[n], g[n]) - pick(M_C3, s[od], g[od]);
+                    ud += pick(M_FD, s[n], g[n]) - pick(M_FD, s[od], g[od]);
+                    d2 += pick(M_C2, s[n2], g[n2]) - pick(M_C2, s[od2], g[od2]);
+                    d4 += pick(M_C4, s[n2], g[n2]) - pick(M_C4, s[od2], g[od2]);
+                    du += pick(M_FU, s[n2], g[n2]) - pick(M_FU, s[od2], g[od2]);
+                    emit(tt);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase B: Gpad = Hl[HL] + Hr[HR] - VF on [qx0, qx1) x [qy0, qy1), into
+    // GV; work item = (row, block of R columns), rows fastest.
+    {
+        const int nrow = qy1 - qy0;
+        const int nblk = (qx1 - qx0 + R - 1) / R;
+        const int dr = NT % nrow, db = NT / nrow;
+        int b = tid / nrow, rr = tid - (tid / nrow) * nrow;
+        for (; b < nblk;) {
+            const int x0 = qx0 + b * R;
+            const int ro = (qy0 + rr - oy) * PITCH - ox;  // + image column
+            float hl[2 * R], hr[2 * R];
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) {
+                hl[i] = HL[ro + x0 - R + i];                        // x0-R .. x0+R-1
+                hr[i] = HR[ro + min(x0 + i, qx1 + R - 1)];          // x0 .. x0+2R-1
+            }
+            float sl_ = hl[0], sr_ = hr[0];
+#pragma unroll
+            for (int i = 1; i <= R; ++i) sl_ += hl[i];
+#pragma unroll
+            for (int i = 1; i <= R; ++i) sr_ += hr[i];
+            GV[ro + x0] = sl_ + sr_ - VF[ro + x0];
+#pragma unroll
+            for (int tt = 1; tt < R; ++tt) {
+                if (x0 + tt < qx1) {
+                    sl_ += hl[R + tt] - hl[tt - 1];
+                    sr_ += hr[R + tt] - hr[tt - 1];
+                    GV[ro + x0 + tt] = sl_ + sr_ - VF[ro + x0 + tt];
+                }
+            }
+            rr += dr;
+            b += db;
+            if (rr >= nrow) {
+                rr -= nrow;
+                ++b;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase C: fold the halo onto edge pixels (adjoint of the clamp), store.
+    float *g = a.g + plane_off;
+    const int xe = min(W, X0 + TW), ye = min(H, Y0 + TH);
+    if (x >= X0 && x < xe) {
+        const int xa = x == 0 ? -R : x, xb = x == W - 1 ? W - 1 + R : x;
+        for (int y = Y0 + ly; y < ye; y += NY) {
+            const int ya = y == 0 ? -R : y, yb = y == H - 1 ? H - 1 + R : y;
+            float acc;
+            if (ya == yb && xa == xb) {
+                acc = GV[(y - oy) * PITCH + lx];
+            } else {
+                acc = 0.f;
+                for (int qy = ya; qy <= yb; ++qy)
+                    for (int qx = xa; qx <= xb; ++qx) acc += GV[(qy - oy) * PITCH + (qx - ox)];
+            }
+            g[(size_t)y * W + x] = acc;
+        }
+    }
+}
+
+// Region of the fixed adjoint kernel for radius r (width 64, 512 threads),
+// or 0 when the generic kernel serves r.
+static int adjoint_fixed_rows(int r) {
+    switch (r) {
+        case 1: case 2: case 3: case 4: return 48;
+        case 5: case 8: return 64;
+        default: return 0;
+    }
+}
+
+size_t adjoint_fixed_lds_bytes(int rh) { return (size_t)rh * 65 * (4 * sizeof(float) + 1); }
+
+bool adjoint_fixed_tile(int r, int *tw, int *th) {
+    const int rh = adjoint_fixed_rows(r);
+    if (!rh) return false;
+    *tw = ((64 - 4 * r) / r) * r;
+    *th = ((rh - 4 * r) / r) * r;
+    return true;
+}
+
+template <int R, int RH>
+static hipError_t launch_adjoint_fixed(const BwdLaunch &a, hipStream_t stream) {
+    const size_t lds = adjoint_fixed_lds_bytes(RH);
+    const void *fn = (const void *)adjoint_fixed_kernel<R, 64, RH, 512>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int blocks = a.tiles_x * a.tiles_y * a.planes;
+    hipLaunchKernelGGL((adjoint_fixed_kernel<R, 64, RH, 512>), dim3(blocks), dim3(512), lds, stream, a);
+    return hipGetLastError();
+}
+
 // LDS layout of the adjoint kernel for a TW x TH tile: five arrays covering
 // the tile grown by 2r on every side.
 void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr) {
@@ -203,6 +422,17 @@ void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr) {
 }
 
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t stream) {
+    if (a.fixed) {
+        switch (a.r) {
+            case 1: return launch_adjoint_fixed<1, 48>(a, stream);
+            case 2: return launch_adjoint_fixed<2, 48>(a, stream);
+            case 3: return launch_adjoint_fixed<3, 48>(a, stream);
+            case 4: return launch_adjoint_fixed<4, 48>(a, stream);
+            case 5: return launch_adjoint_fixed<5, 64>(a, stream);
+            case 8: return launch_adjoint_fixed<8, 64>(a, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
     const size_t lds = (size_t)5 * a.arr * sizeof(float);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)adjoint_kernel,

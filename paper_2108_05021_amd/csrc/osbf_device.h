@@ -88,4 +88,13 @@ __device__ __forceinline__ Pick select8(const float d[8]) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// XCD-aware tile order: the 8 XCDs take workgroups round-robin, so linear
+// workgroup b runs on XCD b % 8.  Give each XCD a contiguous run of tiles so
+// neighbouring tiles (which share halo rows) hit the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = n >> 3, rem = n & 7;
+    return xcd * q + min(xcd, rem) + idx;
+}
+
 }  // namespace osbf

@@ -286,15 +286,6 @@ __device__ __forceinline__ void fwd_tile(const FwdLaunch &a, int tile_x, int til
     }
 }
 
-// XCD-aware tile order: the 8 XCDs take workgroups round-robin, so linear
-// workgroup b runs on XCD b % 8.  Give each XCD a contiguous run of tiles so
-// neighbouring tiles (which share halo rows) hit the same L2.
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-    const int xcd = b & 7, idx = b >> 3;
-    const int q = n >> 3, rem = n & 7;
-    return xcd * q + min(xcd, rem) + idx;
-}
-
 template <int DT, int R, bool SEL, int MODE = 0>
 __global__ __launch_bounds__(256) void fwd_tile_kernel(FwdLaunch a) {
     extern __shared__ float lds[];

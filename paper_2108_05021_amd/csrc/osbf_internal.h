@@ -40,10 +40,14 @@ struct BwdLaunch {
     float *g;             // [planes][H][W] G^t, never aliases gnext
     int planes, H, W, r;
     int tw, th, tiles_x, tiles_y;
-    int pitch, arr;       // LDS layout (bwd_lds_layout)
+    int pitch, arr;       // LDS layout of the generic kernel (bwd_lds_layout)
+    int fixed;            // 1: fixed-geometry kernel (adjoint_fixed_tile)
 };
 
 void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr);
+// Tile of the fixed-geometry adjoint kernel for radius r (false if r is
+// served by the generic kernel).
+bool adjoint_fixed_tile(int r, int *tw, int *th);
 
 // Batched rounds (64x48 fixed geometry, 512 threads).
 size_t batched_lds_bytes();

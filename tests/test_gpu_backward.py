@@ -24,7 +24,7 @@ def _tol(g):
 
 @pytest.mark.parametrize("shape", [(1, 150, 197), (2, 67, 300), (3, 33, 45), (1, 1, 50), (1, 50, 1), (1, 1, 1),
                                    (1, 7, 7)])
-@pytest.mark.parametrize("r", [1, 2, 3, 5, 8, 13, 16])
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8, 13, 16])
 def test_single_adjoint_sweep(dev, shape, r):
     rng = np.random.default_rng(hash((shape, r)) % 2**32)
     img = synth.voronoi(shape[1], shape[2], 6, 0.05, rng, C=shape[0])
@@ -36,6 +36,53 @@ def test_single_adjoint_sweep(dev, shape, r):
     gp = g.reshape(-1, shape[1], shape[2])
     want = np.stack([oracle.adjoint(gp[p].astype(np.float64), s[p], r) for p in range(gp.shape[0])])
     np.testing.assert_allclose(gx.reshape(want.shape), want, rtol=0, atol=_tol(want))
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("shape", [(2, 150, 197), (1, 1, 1), (1, 5, 300), (1, 300, 5), (1, 97, 64)])
+def test_fixed_adjoint_matches_generic(dev, monkeypatch, shape, r):
+    """The fixed-geometry adjoint and the generic one perform the same FP32
+    operations in the same order, so their gradients agree bit for bit."""
+    rng = np.random.default_rng(30 + r)
+    img = synth.voronoi(shape[1], shape[2], 6, 0.05, rng, C=shape[0])
+    _, sel = osbf.forward(_gpu(img, dev), r, 1, return_sel=True)
+    g = _gpu(rng.normal(size=img.shape), dev)
+    fixed = osbf.backward(g, r, 1, sel=sel)
+    monkeypatch.setenv("OSBF_ADJOINT", "generic")
+    generic = osbf.backward(g, r, 1, sel=sel)
+    assert torch.equal(fixed, generic)
+
+
+def test_adjoint_full_size_properties(dev, monkeypatch):
+    """32x3x512x512, r=3 (the fwd+bwd workload): one adjoint sweep conserves
+    the gradient's sum, matches the generic kernel bit for bit, and matches
+    the oracle on sampled 24x24 crops (each crop's outputs only depend on the
+    gradient and maps within r of it, which the crop's oracle run sees)."""
+    r = 3
+    rng = np.random.default_rng(55)
+    x = torch.from_numpy(synth.workload_grad()[0]).to(dev)
+    n, c, h, w = x.shape
+    x = x.reshape(n * c, h, w)
+    _, sel = osbf.forward(x, r, 1, return_sel=True)
+    g = torch.from_numpy(rng.normal(size=(n * c, h, w)).astype(np.float32)).to(dev)
+    gx = osbf.backward(g, r, 1, sel=sel)
+    tot = float(g.double().sum())
+    assert float(gx.double().sum()) == pytest.approx(tot, rel=1e-5, abs=1e-2)
+    monkeypatch.setenv("OSBF_ADJOINT", "generic")
+    assert torch.equal(osbf.backward(g, r, 1, sel=sel), gx)
+    s_all = sel[0]
+    for p, y0, x0 in [(0, 0, 0), (17, 200, 333), (95, 512 - 24, 512 - 24), (50, 0, 300)]:
+        # crop grown by 2r (clipped): an output reads gradient and maps within
+        # r of it, and crop edges that are image edges fold as in the image
+        ya, yb = max(0, y0 - 2 * r), min(h, y0 + 24 + 2 * r)
+        xa, xb = max(0, x0 - 2 * r), min(w, x0 + 24 + 2 * r)
+        gg = g[p, ya:yb, xa:xb].double().cpu().numpy()
+        ss = s_all[p, ya:yb, xa:xb].cpu().numpy()
+        want = oracle.adjoint(gg, ss, r)
+        cy0, cx0 = y0 - ya, x0 - xa
+        got = gx[p, y0:y0 + 24, x0:x0 + 24].cpu().numpy()
+        ref = want[cy0:cy0 + 24, cx0:cx0 + 24]
+        np.testing.assert_allclose(got, ref, rtol=0, atol=_tol(ref))
 
 
 @pytest.mark.parametrize("r", [1, 3, 6])
