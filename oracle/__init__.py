@@ -9,7 +9,9 @@ precision, see its header for every reading of the paper); this module only
 builds that file with gcc and marshals numpy arrays into it.  ``exact.py``
 holds an exact-rational brute force for tiny inputs.
 
-Window index order (= tie order): R, L, D, U, SE, SW, NE, NW.
+Window index order (= tie order): R, L, D, U, SE, SW, NE, NW.  The volume
+filter (``osbf3d_oracle.c``) has 14 windows: +x, -x, +y, -y, +z, -z, then the
+octants with x varying fastest and + before -.
 """
 from __future__ import annotations
 
@@ -21,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "osbf_oracle.c")
+_SRC3 = os.path.join(_HERE, "osbf3d_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libosbf_oracle.so")
 
 WINDOWS = ("R", "L", "D", "U", "SE", "SW", "NE", "NW")
@@ -33,7 +36,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-               "-o", tmp, _SRC, "-lm"]
+               "-o", tmp, _SRC, _SRC3, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -43,7 +46,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
+                                                                          os.path.getmtime(_SRC3)):
         build(force=True)
     lib = ctypes.CDLL(_LIB_PATH)
     d = ctypes.POINTER(ctypes.c_double)
@@ -72,6 +76,14 @@ def _load():
     lib.oracle_box_forward.restype = ci
     lib.oracle_window_extent.argtypes = [ci, ci, ci, ci] + [ctypes.POINTER(ci)] * 4
     lib.oracle_window_extent.restype = None
+    lib.oracle3d_window_extent.argtypes = [ci, ci, ci, ci, ci, ctypes.POINTER(ci)]
+    lib.oracle3d_window_extent.restype = None
+    lib.oracle3d_sweep.argtypes = [d, d, u8, d, d, ci, ci, ci, ci, ci]
+    lib.oracle3d_sweep.restype = None
+    lib.oracle3d_forward.argtypes = [d, d, u8, ci, ci, ci, ci, ci, ci, ci]
+    lib.oracle3d_forward.restype = ci
+    lib.oracle3d_select_int64.argtypes = [i64, u8, i64, ci, ci, ci, ci]
+    lib.oracle3d_select_int64.restype = None
     _lib = lib
     return lib
 
@@ -222,3 +234,63 @@ def box_forward(x, r: int, T: int):
     if _load().oracle_box_forward(_pd(a), _pd(out), P, H, W, r, T) != 0:
         raise ValueError("oracle_box_forward failed")
     return out.reshape(shape)
+
+
+# ----------------------------------------------------------------- volumes
+
+WINDOWS3 = ("+x", "-x", "+y", "-y", "+z", "-z",
+            "+x+y+z", "-x+y+z", "+x-y+z", "-x-y+z", "+x+y-z", "-x+y-z", "+x-y-z", "-x-y-z")
+
+
+def _volumes(x):
+    """View an array of shape (D,H,W) or (V,D,H,W) as (V,D,H,W) FP64."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    if a.ndim == 3:
+        return a.reshape(1, *a.shape)
+    return a.reshape(-1, *a.shape[-3:])
+
+
+def window_extent3(w: int, x: int, y: int, z: int, r: int):
+    """Voxel set [x0,x1] x [y0,y1] x [z0,z1] of volume window ``w``."""
+    e = (ctypes.c_int * 6)()
+    _load().oracle3d_window_extent(w, x, y, z, r, e)
+    return tuple(e)
+
+
+def forward3d(x, r: int, T: int, *, return_sel: bool = False, nthreads: int = 0):
+    """T sweeps of the volume filter (clamp boundary in x, y, z).  ``x`` is
+    (D,H,W) or (V,D,H,W); with ``return_sel`` also the maps [T][V][D][H][W]."""
+    shape = np.shape(x)
+    a = _volumes(x)
+    V, D, H, W = a.shape
+    out = np.empty_like(a)
+    sel = np.empty((T, V, D, H, W), np.uint8) if return_sel else None
+    if _load().oracle3d_forward(_pd(a), _pd(out), _pu8(sel), V, D, H, W, r, T, nthreads) != 0:
+        raise ValueError("oracle3d_forward failed")
+    out = out.reshape(shape)
+    return (out, sel) if return_sel else out
+
+
+def sweep3d(u, r: int, *, nthreads: int = 0, return_means: bool = False):
+    """One sweep on one volume: (next, sel [D,H,W], err [D,H,W,14]) and with
+    ``return_means`` the 14 window means [D,H,W,14]."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    D, H, W = u.shape
+    out = np.empty_like(u)
+    sel = np.empty((D, H, W), np.uint8)
+    err = np.empty((D, H, W, 14), np.float64)
+    means = np.empty((D, H, W, 14), np.float64) if return_means else None
+    _load().oracle3d_sweep(_pd(u), _pd(out), _pu8(sel), _pd(err),
+                           None if means is None else _pd(means), D, H, W, r, nthreads)
+    return (out, sel, err, means) if return_means else (out, sel, err)
+
+
+def select_int64_3d(x, r: int):
+    """Exact integer selection for one volume sweep: (sel, sums [D,H,W,14])."""
+    a = np.ascontiguousarray(x, dtype=np.int64)
+    D, H, W = a.shape
+    sel = np.empty((D, H, W), np.uint8)
+    sums = np.empty((D, H, W, 14), np.int64)
+    _load().oracle3d_select_int64(a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _pu8(sel),
+                                  sums.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), D, H, W, r)
+    return sel, sums

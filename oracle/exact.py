@@ -63,3 +63,70 @@ def forward(img, r: int, T: int):
         u, s = sweep(u, r)
         sels.append(s)
     return u, sels
+
+
+# ----------------------------------------------------------------- volumes
+# Sec. "Higher Dimension Case": along each axis a window is one-sided towards
+# + ([c, c+r]), towards - ([c-r, c]) or full ([c-r, c+r]).  Six halves take one
+# axis one-sided and two full; eight octants are one-sided along all three.
+# Order (= tie order): +x, -x, +y, -y, +z, -z, then octants with x varying
+# fastest and + before - on every axis.
+
+def _sides3():
+    halves = []
+    for axis in range(3):
+        for s in (1, -1):
+            side = [0, 0, 0]
+            side[axis] = s
+            halves.append(tuple(side))
+    octants = [(sx, sy, sz) for sz in (1, -1) for sy in (1, -1) for sx in (1, -1)]
+    return halves + octants
+
+
+SIDES3 = _sides3()
+
+
+def _range(c: int, s: int, r: int):
+    return range(c, c + r + 1) if s > 0 else range(c - r, c + 1) if s < 0 else range(c - r, c + r + 1)
+
+
+def window_mean3(u, side, x: int, y: int, z: int, r: int) -> Fraction:
+    D, H, W = len(u), len(u[0]), len(u[0][0])
+    total = Fraction(0)
+    count = 0
+    for zz in _range(z, side[2], r):
+        for yy in _range(y, side[1], r):
+            for xx in _range(x, side[0], r):
+                total += u[min(max(zz, 0), D - 1)][min(max(yy, 0), H - 1)][min(max(xx, 0), W - 1)]
+                count += 1
+    return total / count
+
+
+def sweep3(u, r: int):
+    """One Jacobi sweep on a volume u[z][y][x]; returns (next, selection)."""
+    D, H, W = len(u), len(u[0]), len(u[0][0])
+    nxt = [[[Fraction(0)] * W for _ in range(H)] for _ in range(D)]
+    sel = [[[0] * W for _ in range(H)] for _ in range(D)]
+    for z in range(D):
+        for y in range(H):
+            for x in range(W):
+                c = u[z][y][x]
+                best = None
+                for i, side in enumerate(SIDES3):
+                    mean = window_mean3(u, side, x, y, z, r)
+                    dist = abs(mean - c)
+                    if best is None or dist < best[0]:
+                        best = (dist, i, mean)
+                nxt[z][y][x] = best[2]
+                sel[z][y][x] = best[1]
+    return nxt, sel
+
+
+def forward3(vol, r: int, T: int):
+    """T sweeps on a volume; returns (U^T, [sel_t])."""
+    u = [[[Fraction(v) for v in row] for row in sl] for sl in vol]
+    sels = []
+    for _ in range(T):
+        u, s = sweep3(u, r)
+        sels.append(s)
+    return u, sels

@@ -16,6 +16,8 @@ clipping):
   voronoi(H, W, K, ...)     K uniform sites, each pixel takes the level of its
                             nearest site (K random convex polygons), levels
                             uniform in [0, 1] per region and channel.
+  voronoi3d(D, H, W, K, ...) the same in a volume (K random convex polyhedra),
+                            standing in for the paper's MRI volume.
 """
 from __future__ import annotations
 
@@ -23,7 +25,8 @@ import numpy as np
 
 __all__ = [
     "rectangles", "voronoi", "workload_single", "workload_rgb", "workload_batched",
-    "workload_precision", "workload_grad", "integer_image", "dyadic_rectangles",
+    "workload_precision", "workload_grad", "voronoi3d", "workload_volume", "integer_image",
+    "dyadic_rectangles",
 ]
 
 
@@ -69,6 +72,27 @@ def voronoi(H: int, W: int, K: int, sigma: float, rng, C: int = 1) -> np.ndarray
     return out
 
 
+def voronoi3d(D: int, H: int, W: int, K: int, sigma: float, rng) -> np.ndarray:
+    """(D, H, W) float32 Voronoi piecewise-constant volume plus Gaussian noise."""
+    from scipy.spatial import cKDTree
+
+    sites = np.stack([rng.uniform(0, D, K), rng.uniform(0, H, K), rng.uniform(0, W, K)], axis=1)
+    tree = cKDTree(sites)
+    levels = rng.uniform(0.0, 1.0, size=K)
+    out = np.empty((D, H, W), np.float32)
+    yy, xx = np.meshgrid(np.arange(H, dtype=np.float64) + 0.5, np.arange(W, dtype=np.float64) + 0.5,
+                         indexing="ij")
+    step = max(1, (1 << 22) // max(H * W, 1))
+    for z0 in range(0, D, step):
+        z1 = min(D, z0 + step)
+        zz = np.repeat(np.arange(z0, z1, dtype=np.float64) + 0.5, H * W)
+        pts = np.stack([zz, np.tile(yy.ravel(), z1 - z0), np.tile(xx.ravel(), z1 - z0)], axis=1)
+        _, idx = tree.query(pts, workers=-1)
+        out[z0:z1] = levels[idx].reshape(z1 - z0, H, W)
+    out += rng.normal(0.0, sigma, size=out.shape).astype(np.float32)
+    return out
+
+
 # ---------------------------------------------------------------- workloads
 
 def workload_single(seed: int = 1) -> np.ndarray:
@@ -110,6 +134,11 @@ def workload_grad(seed: int = 5, N: int = 32, C: int = 3, H: int = 512, W: int =
     x = np.stack([voronoi(H, W, 64, 0.05, rng, C=C) for _ in range(N)])
     w = np.random.default_rng(weight_seed).normal(0.0, 1.0, size=x.shape).astype(np.float32)
     return x, w
+
+
+def workload_volume(seed: int = 6, D: int = 256, H: int = 256, W: int = 256) -> np.ndarray:
+    """256^3 FP32 volume: Voronoi K=64, sigma 0.05 (r in {1,2,3}, T=10)."""
+    return voronoi3d(D, H, W, 64, 0.05, np.random.default_rng(seed))
 
 
 # ------------------------------------------------------- test-only helpers
