@@ -51,6 +51,7 @@ extern "C" {
 
 #define OSBF_ABI_VERSION 1
 #define OSBF_MAX_RADIUS 32          /* largest supported r */
+#define OSBF3D_MAX_RADIUS 4         /* largest r of the volume filter */
 
 typedef enum {
     OSBF_SUCCESS = 0,
@@ -225,6 +226,45 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osb
                               int32_t radius, int32_t iterations, int32_t ck,
                               int32_t *tile_w, int32_t *tile_h, int32_t *fused,
                               int32_t *launches);
+
+/*
+ * Volume filter (Sec. "Higher Dimension Case").  The one-sided kernels along
+ * x, y and z span 14 windows per voxel, every one containing the voxel:
+ *   0 +x, 1 -x, 2 +y, 3 -y, 4 +z, 5 -z   halves: one axis [c, c+r] or
+ *                                        [c-r, c], the other two [c-r, c+r];
+ *                                        (r+1)(2r+1)^2 voxels
+ *   6 (+x,+y,+z), 7 (-x,+y,+z), 8 (+x,-y,+z), 9 (-x,-y,+z),
+ *  10 (+x,+y,-z), 11 (-x,+y,-z), 12 (+x,-y,-z), 13 (-x,-y,-z)
+ *                                        octants, one-sided on all three axes;
+ *                                        (r+1)^3 voxels
+ * Each sweep replaces every voxel by the mean of the window whose mean is
+ * closest to it (first in the order above on ties), reading the replicate
+ * extension of the previous iterate (clamp in x, y and z); T Jacobi sweeps.
+ * The index order is this library's reading (the paper names the six halves
+ * but orders none of the windows); it extends the planar order.
+ */
+
+/* Workspace bytes osbf3d_forward needs (0 if none), (size_t)-1 if invalid. */
+size_t osbf3d_forward_workspace_size(int32_t volumes, int32_t depth, int32_t height, int32_t width,
+                                     int32_t radius, int32_t iterations);
+
+/*
+ * osbf3d_forward -- T sweeps of the volume filter on `volumes` FP32 volumes.
+ *   src, dst   device, [volumes][depth][height][width] contiguous FP32
+ *              (x fastest, then y, then z); src == dst allowed (in place)
+ *   radius     0..OSBF3D_MAX_RADIUS (0 or iterations = 0: copy);
+ *              larger radii return OSBF_ERROR_UNSUPPORTED
+ *   sel        nullable device [iterations][volumes][depth][height][width]
+ *              uint8 window indices (0..13) of every sweep
+ *   ws         device workspace of osbf3d_forward_workspace_size bytes
+ *              (one FP32 volume set; needed when iterations >= 2 or in place)
+ * Stream-ordered and asynchronous; arguments are checked before any launch.
+ * Arithmetic is FP32 (sums, selection and means); results match an FP64
+ * evaluation up to FP32 rounding and near-tie selections.
+ */
+osbf_status osbf3d_forward(const float *src, float *dst, int32_t volumes, int32_t depth,
+                           int32_t height, int32_t width, int32_t radius, int32_t iterations,
+                           uint8_t *sel, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

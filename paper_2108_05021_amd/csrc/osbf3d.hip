@@ -1,0 +1,268 @@
+// One-sided box filter on volumes (Sec. "Higher Dimension Case"), gfx950.
+//
+// Fourteen windows per voxel: six halves (one axis one-sided, two full) and
+// eight octants (one-sided along all three axes).  Each is a z-sum of a
+// planar quantity of the slices it spans:
+//   octant (sx,sy,sz) = sum over the sz side in z of the planar quadrant (sx,sy)
+//   half +-x / +-y    = sum over the full z range of the planar half
+//   half +-z          = sum over the z side of the planar (2r+1)^2 box
+// A workgroup owns a TW x TH column of voxels and a chunk of slices, and
+// streams through the slices (2.5D blocking): per slice it loads the clamped
+// planar region into LDS, forms the planar running-sum fields V, Q, H of the
+// planar kernels, and every thread derives the nine planar quantities of its
+// (x, y) column (4 quadrants, 4 halves, the box) into a register ring of the
+// last 2r+1 slices.  Once the ring spans [z-r, z+r] the thread sums it along
+// z, selects among the 14 windows (scaled distances, tie order +x, -x, +y, -y,
+// +z, -z, then octants with x fastest and + first) and writes voxel z.
+// The next slice's global loads are issued before the current slice's LDS
+// work; the planar region is double-buffered, so three barriers per slice.
+#include <type_traits>
+
+#include "osbf_device.h"
+#include "osbf_fwd_device.h"
+#include "osbf_internal.h"
+
+namespace osbf {
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// Q on columns [xa, xb+R), rows [ya, yb+R) and H on the same columns, rows
+// [ya, yb), like fixed_phase_qh, but with (row, block of R columns) work items
+// spread over all lanes: the 3D region is only TH + 2R rows tall.
+template <int R, int RW, int NT, bool CL>
+__device__ __forceinline__ void phase_qh_items(const float *P, const float *V, float *Q, float *Hs,
+                                               int tid, int ox, int oy, int W, int xa, int xb,
+                                               int ya, int yb) {
+    constexpr int PITCH = RW + 1;
+    const int xend = xb + R, yend = yb + R;
+    const int nr = yend - ya, nb = (xend - xa + R - 1) / R;
+    const int lo = CL ? max(0, xa - R) : xa - R;
+    const int hi = CL ? min(W, xend) - 1 : xend - 1;
+    const int dr = NT % nr, db = NT / nr;
+    int b = tid / nr, row = tid - b * nr;
+    while (b < nb) {
+        const int y = ya + row;
+        const bool doH = y < yb;
+        const int x0 = xa + b * R;
+        const int rb = (y - oy) * PITCH - ox;  // + image column
+        float v[2 * R], p[2 * R];
+#pragma unroll
+        for (int t = 0; t < 2 * R; ++t) {
+            const int col = min(max(x0 - R + t, lo), hi);
+            v[t] = V[rb + col];
+            p[t] = P[rb + col];
+        }
+        float q = v[0], h = p[0];
+#pragma unroll
+        for (int t = 1; t <= R; ++t) {
+            q += v[t];
+            h += p[t];
+        }
+        Q[rb + x0] = q;
+        if (doH) Hs[rb + x0] = h;
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+            if (x0 + t < xend) {
+                q += v[R + t] - v[t - 1];
+                h += p[R + t] - p[t - 1];
+                Q[rb + x0 + t] = q;
+                if (doH) Hs[rb + x0 + t] = h;
+            }
+        }
+        row += dr;
+        b += db;
+        if (row >= nr) {
+            row -= nr;
+            ++b;
+        }
+    }
+}
+
+// Planar quantities of one slice at region offset o: the halves +x, -x, +y,
+// -y, the (2R+1)^2 box and the quadrants (+,+), (-,+), (+,-), (-,-).
+enum : int { Q_R = 0, Q_L, Q_D, Q_U, Q_BOX, Q_SE, Q_SW, Q_NE, Q_NW, NQ };
+
+template <int R, int PITCH>
+__device__ __forceinline__ void planar_quantities(const float *P, const float *V, const float *Q,
+                                                  const float *Hs, int o, float q[NQ], float &c) {
+    constexpr int RD = R * PITCH;
+    c = P[o];
+    const float nw = Q[o], ne = Q[o + R], sw = Q[o + RD], se = Q[o + RD + R];
+    const float hl = Hs[o], hr = Hs[o + R], vu = V[o], vd = V[o + RD];
+    q[Q_R] = ne + se - hr;
+    q[Q_L] = nw + sw - hl;
+    q[Q_D] = sw + se - vd;
+    q[Q_U] = nw + ne - vu;
+    q[Q_BOX] = box_sum(nw, ne, sw, se, hl, hr, vu, vd, c);
+    q[Q_SE] = se;
+    q[Q_SW] = sw;
+    q[Q_NE] = ne;
+    q[Q_NW] = nw;
+}
+
+template <int R, int NT, bool SEL>
+__global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
+    constexpr int RW = 64, PITCH = RW + 1, NY = NT / RW, TH = NY, RH = TH + 2 * R;
+    constexpr int ARR = RH * PITCH, NL = (RH + NY - 1) / NY, RING = 2 * R + 1;
+    extern __shared__ float lds[];
+    float *const V = lds + 2 * ARR;
+    float *const Q = lds + 3 * ARR;
+    float *const Hs = lds + 4 * ARR;
+    const int tid = threadIdx.x, lx = tid % RW;
+    const int ly = __builtin_amdgcn_readfirstlane(tid / RW);
+    const int D = a.D, H = a.H, W = a.W, TW = a.tw;
+    const int per_vol = a.tiles_x * a.tiles_y * a.chunks;
+    const int t = xcd_remap(blockIdx.x, per_vol * a.vols);
+    const int vol = t / per_vol;
+    int rem = t - vol * per_vol;
+    const int chunk = rem / (a.tiles_x * a.tiles_y);
+    rem -= chunk * (a.tiles_x * a.tiles_y);
+    const int tile_y = rem / a.tiles_x, tile_x = rem - tile_y * a.tiles_x;
+    const int X0 = tile_x * TW, Y0 = tile_y * TH;
+    const int ox = X0 - R, oy = Y0 - R;
+    const int xa = X0, xb = min(W, X0 + TW), ya = Y0, yb = min(H, Y0 + TH);
+    const bool interior = X0 - R >= 0 && Y0 - R >= 0 && X0 + TW + R <= W && Y0 + TH + R <= H;
+    const int z0 = chunk * a.zc, z1 = min(D, z0 + a.zc);
+    const int nsl = (z1 - z0) + 2 * R;  // slices z0-R .. z1+R-1
+    const size_t slice = (size_t)H * W;
+    const float *src = a.src + (size_t)vol * D * slice;
+    float *dst = a.dst + (size_t)vol * D * slice;
+    uint8_t *sel = SEL ? a.sel + (size_t)vol * D * slice : nullptr;
+
+    // this thread's (x, y) column and its loads of the planar region
+    const int x = ox + lx, y = Y0 + ly;
+    const bool own = x >= xa && x < xb && y < yb;
+    const bool ldx = x >= 0 && x < W && lx < TW + 2 * R;
+    const int ly0 = max(0, oy), ly1 = min(H, Y0 + TH + R);
+    float raw[NL];
+    auto load_slice = [&](int zs) {
+        const float *s = src + (size_t)min(max(zs, 0), D - 1) * slice;
+        if (ldx) {
+#pragma unroll
+            for (int i = 0; i < NL; ++i) raw[i] = s[(size_t)min(ly0 + ly + i * NY, ly1 - 1) * W + x];
+        }
+    };
+    auto store_slice = [&](float *P) {
+        if (ldx) {
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int yy = ly0 + ly + i * NY;
+                if (yy < ly1) P[(yy - oy) * PITCH + lx] = raw[i];
+            }
+        }
+    };
+
+    constexpr float w_h = (float)((R + 1) * (R + 1)), w_o = (float)((2 * R + 1) * (2 * R + 1));
+    constexpr float N = (float)((R + 1) * (R + 1) * (R + 1)) * w_o;
+    const float invN = 1.0f / N;
+    float ring[RING][NQ], cring[RING];
+
+    load_slice(z0 - R);
+    for (int base = 0; base < nsl; base += RING) {
+        static_for<0, RING>([&](auto S) {
+            constexpr int s = decltype(S)::value;
+            const int n = base + s;
+            if (n >= nsl) return;  // uniform over the workgroup
+            float *P = lds + (n & 1) * ARR;
+            store_slice(P);
+            if (n + 1 < nsl) load_slice(z0 - R + n + 1);
+            __syncthreads();
+            if (interior)
+                fixed_phase_v<R, RW, RH, NT, false>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
+            else
+                fixed_phase_v<R, RW, RH, NT, true>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
+            __syncthreads();
+            if (interior)
+                phase_qh_items<R, RW, NT, false>(P, V, Q, Hs, tid, ox, oy, W, xa, xb, ya, yb);
+            else
+                phase_qh_items<R, RW, NT, true>(P, V, Q, Hs, tid, ox, oy, W, xa, xb, ya, yb);
+            __syncthreads();
+            if (!own) return;
+            planar_quantities<R, PITCH>(P, V, Q, Hs, (y - oy) * PITCH + lx, ring[s], cring[s]);
+            if (n < 2 * R) return;
+            // voxel z = z0 + n - 2R: slot of slice z - R + j is (s + 1 + j) % RING
+            constexpr int C = (s + 1 + R) % RING;
+            const float c = cring[C];
+            auto zsum = [&](int k, int j0, int j1) {
+                float acc = ring[(s + 1 + j0) % RING][k];
+#pragma unroll
+                for (int j = j0 + 1; j <= j1; ++j) acc += ring[(s + 1 + j) % RING][k];
+                return acc;
+            };
+            float d[14];
+            const float nc = -N * c;
+            d[0] = fmaf(w_h, zsum(Q_R, 0, 2 * R), nc);
+            d[1] = fmaf(w_h, zsum(Q_L, 0, 2 * R), nc);
+            d[2] = fmaf(w_h, zsum(Q_D, 0, 2 * R), nc);
+            d[3] = fmaf(w_h, zsum(Q_U, 0, 2 * R), nc);
+            d[4] = fmaf(w_h, zsum(Q_BOX, R, 2 * R), nc);
+            d[5] = fmaf(w_h, zsum(Q_BOX, 0, R), nc);
+            d[6] = fmaf(w_o, zsum(Q_SE, R, 2 * R), nc);
+            d[7] = fmaf(w_o, zsum(Q_SW, R, 2 * R), nc);
+            d[8] = fmaf(w_o, zsum(Q_NE, R, 2 * R), nc);
+            d[9] = fmaf(w_o, zsum(Q_NW, R, 2 * R), nc);
+            d[10] = fmaf(w_o, zsum(Q_SE, 0, R), nc);
+            d[11] = fmaf(w_o, zsum(Q_SW, 0, R), nc);
+            d[12] = fmaf(w_o, zsum(Q_NE, 0, R), nc);
+            d[13] = fmaf(w_o, zsum(Q_NW, 0, R), nc);
+            // balanced tournament, the lower-numbered entrant wins ties
+            float e0 = d[0], e1 = d[2], e2 = d[4], e3 = d[6], e4 = d[8], e5 = d[10], e6 = d[12];
+            int i0 = 0, i1 = 2, i2 = 4, i3 = 6, i4 = 8, i5 = 10, i6 = 12;
+            duel(e0, i0, d[1], 1);
+            duel(e1, i1, d[3], 3);
+            duel(e2, i2, d[5], 5);
+            duel(e3, i3, d[7], 7);
+            duel(e4, i4, d[9], 9);
+            duel(e5, i5, d[11], 11);
+            duel(e6, i6, d[13], 13);
+            duel(e0, i0, e1, i1);
+            duel(e2, i2, e3, i3);
+            duel(e4, i4, e5, i5);
+            duel(e0, i0, e2, i2);
+            duel(e4, i4, e6, i6);
+            duel(e0, i0, e4, i4);
+            const int z = z0 + n - 2 * R;
+            const size_t gi = (size_t)z * slice + (size_t)y * W + x;
+            dst[gi] = fmaf(e0, invN, c);
+            if (SEL) sel[gi] = (uint8_t)i0;
+        });
+    }
+}
+
+bool fwd3d_radius(int r) { return r >= 1 && r <= 4; }
+
+void fwd3d_geometry(int r, int *tw, int *th) {
+    *tw = 64 - 2 * r;
+    *th = 512 / 64;
+}
+
+size_t fwd3d_lds_bytes(int r) { return (size_t)5 * (512 / 64 + 2 * r) * 65 * sizeof(float); }
+
+template <int R>
+static hipError_t launch3d(const Fwd3dLaunch &a, hipStream_t stream) {
+    const int blocks = a.tiles_x * a.tiles_y * a.chunks * a.vols;
+    const size_t lds = fwd3d_lds_bytes(R);
+    if (a.sel)
+        hipLaunchKernelGGL((fwd3d_kernel<R, 512, true>), dim3(blocks), dim3(512), lds, stream, a);
+    else
+        hipLaunchKernelGGL((fwd3d_kernel<R, 512, false>), dim3(blocks), dim3(512), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward3d(const Fwd3dLaunch &a, hipStream_t stream) {
+    switch (a.r) {
+        case 1: return launch3d<1>(a, stream);
+        case 2: return launch3d<2>(a, stream);
+        case 3: return launch3d<3>(a, stream);
+        case 4: return launch3d<4>(a, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace osbf

@@ -707,4 +707,69 @@ osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype, os
     return osbf_batched_launch(&b, stream_);
 }
 
+
+size_t osbf3d_forward_workspace_size(int32_t vols, int32_t D, int32_t H, int32_t W, int32_t r,
+                                     int32_t T) {
+    if (vols < 1 || D < 1 || H < 1 || W < 1 || r < 0 || r > OSBF3D_MAX_RADIUS || T < 0) return (size_t)-1;
+    if (T == 0 || r == 0) return 0;
+    return (size_t)vols * D * H * W * sizeof(float);
+}
+
+osbf_status osbf3d_forward(const float *src, float *dst, int32_t vols, int32_t D, int32_t H,
+                           int32_t W, int32_t r, int32_t T, uint8_t *sel, void *ws,
+                           size_t ws_bytes, void *stream_) {
+    g_last_error.clear();
+    if (vols < 1 || D < 1 || H < 1 || W < 1)
+        return fail(OSBF_ERROR_INVALID_VALUE, "volumes, depth, height and width must be >= 1 (got %d, %d, %d, %d)",
+                    vols, D, H, W);
+    if ((long long)D * H * W > (1LL << 40)) return fail(OSBF_ERROR_INVALID_VALUE, "volume too large");
+    if (r < 0) return fail(OSBF_ERROR_INVALID_VALUE, "radius %d < 0", r);
+    if (r > OSBF3D_MAX_RADIUS)
+        return fail(OSBF_ERROR_UNSUPPORTED, "volume radius %d above %d", r, OSBF3D_MAX_RADIUS);
+    if (T < 0) return fail(OSBF_ERROR_INVALID_VALUE, "iterations %d < 0", T);
+    if (!src || !dst) return fail(OSBF_ERROR_INVALID_VALUE, "src and dst must be non-NULL");
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t nvox = (size_t)vols * D * H * W;
+    const size_t bytes = nvox * sizeof(float);
+    hipError_t e;
+    if (T == 0 || r == 0) {
+        if (src != dst && (e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy");
+        if (sel && T > 0 && (e = hipMemsetAsync(sel, 0, (size_t)T * nvox, stream)) != hipSuccess)
+            return hip_fail(e, "memset sel");
+        return OSBF_SUCCESS;
+    }
+    if ((T >= 2 || src == dst) && (!ws || ws_bytes < bytes))
+        return fail(OSBF_ERROR_WORKSPACE, "workspace of %zu bytes required, got %zu", bytes, ws ? ws_bytes : 0);
+
+    Fwd3dLaunch a;
+    int th;
+    fwd3d_geometry(r, &a.tw, &th);
+    a.vols = vols; a.D = D; a.H = H; a.W = W; a.r = r;
+    a.tiles_x = (W + a.tw - 1) / a.tw;
+    a.tiles_y = (H + th - 1) / th;
+    const long long layer = (long long)a.tiles_x * a.tiles_y * vols;
+    // slice chunks: about 32 slices each, more chunks only to fill the device
+    long long chunks = std::max(1LL, std::min((long long)(D + 31) / 32, (2048 + layer - 1) / layer));
+    a.zc = (int)((D + chunks - 1) / chunks);
+    a.chunks = (D + a.zc - 1) / a.zc;
+    if (layer * a.chunks >= (1LL << 31)) return fail(OSBF_ERROR_INVALID_VALUE, "too many tiles");
+
+    const float *cur = src;
+    if (src == dst && (T % 2) == 1) {
+        if ((e = hipMemcpyAsync(ws, src, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy to workspace");
+        cur = (const float *)ws;
+    }
+    for (int t = 0; t < T; ++t) {
+        float *out = ((T - 1 - t) % 2 == 0) ? dst : (float *)ws;
+        a.src = cur;
+        a.dst = out;
+        a.sel = sel ? sel + (size_t)t * nvox : nullptr;
+        if ((e = launch_forward3d(a, stream)) != hipSuccess) return hip_fail(e, "volume launch");
+        cur = out;
+    }
+    return OSBF_SUCCESS;
+}
+
 }  // extern "C"

@@ -55,4 +55,19 @@ hipError_t launch_batched_round(int dtype, const FwdLaunch *descs, const uint2 *
                                 int grid, hipStream_t stream);
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t s);
 
+// One sweep of the volume filter over every volume: a workgroup per
+// (volume, slice chunk, tile); tiles are tw x 8 voxel columns.
+struct Fwd3dLaunch {
+    const float *src;     // [vols][D][H][W]
+    float *dst;           // [vols][D][H][W], never aliases src
+    uint8_t *sel;         // nullable [vols][D][H][W] map of this sweep
+    int vols, D, H, W, r;
+    int tw, tiles_x, tiles_y;
+    int zc, chunks;       // slices per workgroup, chunks per volume
+};
+bool fwd3d_radius(int r);
+void fwd3d_geometry(int r, int *tw, int *th);
+size_t fwd3d_lds_bytes(int r);
+hipError_t launch_forward3d(const Fwd3dLaunch &a, hipStream_t s);
+
 }  // namespace osbf

@@ -84,6 +84,10 @@ def lib():
     L.osbf_batched.restype = ctypes.c_int
     L.osbf_forward_plan.argtypes = [i32, i32, i32, ctypes.c_int, i32, i32, i32] + [ctypes.POINTER(i32)] * 4
     L.osbf_forward_plan.restype = ctypes.c_int
+    L.osbf3d_forward_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32]
+    L.osbf3d_forward_workspace_size.restype = sz
+    L.osbf3d_forward.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.osbf3d_forward.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -283,3 +287,24 @@ def forward_fast(x: torch.Tensor, r: int, T: int, *, out: torch.Tensor | None = 
 def box_forward(x: torch.Tensor, r: int, T: int, *, out: torch.Tensor | None = None):
     """T sweeps of the classical (2r+1)^2 box filter (replicate boundary)."""
     return _mode_forward(lib().osbf_box_forward, x, r, T, out)
+
+
+def forward3d(x: torch.Tensor, r: int, T: int, *, return_sel: bool = False,
+              out: torch.Tensor | None = None):
+    """T sweeps of the volume filter (14 windows) on a (..., D, H, W) FP32
+    device tensor; with ``return_sel`` also the uint8 maps [T, *x.shape]."""
+    if x.dim() < 3:
+        raise ValueError("expected (..., D, H, W)")
+    if not x.is_contiguous() or x.dtype != torch.float32:
+        raise ValueError("expected a contiguous float32 tensor")
+    D, H, W = x.shape[-3:]
+    vols = x.numel() // (D * H * W) if D * H * W else 0
+    y = torch.empty_like(x) if out is None else out
+    sel = torch.empty((T, *x.shape), dtype=torch.uint8, device=x.device) if return_sel else None
+    n = int(lib().osbf3d_forward_workspace_size(vols, D, H, W, r, T))
+    if n == (1 << 64) - 1:
+        n = 0  # invalid arguments: the entry point reports the error
+    ws = torch.empty(max(n, 1), dtype=torch.uint8, device=x.device) if n else None
+    _check(lib().osbf3d_forward(_ptr(x), _ptr(y), vols, D, H, W, r, T, _ptr(sel), _ptr(ws),
+                                0 if ws is None else ws.numel(), _stream(x.device)))
+    return (y, sel) if return_sel else y

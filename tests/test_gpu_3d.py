@@ -1,0 +1,155 @@
+"""GPU parity of the volume filter (osbf3d_forward) against the FP64 oracle.
+
+Sweeps are compared teacher-forced, as for the planar filter: the oracle runs
+one sweep on the GPU's own input iterate; every GPU value must equal (within
+1e-5) the oracle's mean of the window the GPU selected, and that window's
+scaled distance may exceed the oracle's minimum by at most
+tau3 = 2^-18 * N * (1 + max|U|), N = (r+1)^3 (2r+1)^2, a bound on the FP32
+rounding of the z-sums of the planar window sums (window sums reach 14
+quantities deep, one level more than the planar filter, hence 2^-18).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_05021_amd import osbf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def tau3(r, u):
+    return 2.0 ** -18 * (r + 1) ** 3 * (2 * r + 1) ** 2 * (1.0 + float(np.abs(u).max()))
+
+
+def check_sweep3d(u_in, u_out, r, sel, tol=1e-5):
+    u_in = np.asarray(u_in, np.float64)
+    u_out = np.asarray(u_out, np.float64)
+    sel = np.asarray(sel).astype(np.int64)
+    assert sel.min() >= 0 and sel.max() <= 13, "selection index out of range"
+    _, sel_o, err, means = oracle.sweep3d(u_in, r, return_means=True)
+    emin = err.min(axis=3)
+    e_gpu = np.take_along_axis(err, sel[..., None], 3)[..., 0]
+    gap = e_gpu - emin
+    t = tau3(r, u_in)
+    assert gap.max() <= t, f"{int((gap > t).sum())} selections not near-minimal (gap {gap.max():.3e} > {t:.3e})"
+    want = np.take_along_axis(means, sel[..., None], 3)[..., 0]
+    dev = np.abs(u_out - want)
+    assert dev.max() <= tol, f"value off the selected mean by {dev.max():.3e}"
+    m_o = np.take_along_axis(means, sel_o[..., None].astype(np.int64), 3)[..., 0]
+    return int(((sel != sel_o) & (np.abs(want - m_o) > tol)).sum())
+
+
+def _vol(shape, seed, K=6, sigma=0.05):
+    rng = np.random.default_rng(seed)
+    return np.stack([synth.voronoi3d(*shape[-3:], K, sigma, rng) for _ in range(int(np.prod(shape[:-3])) or 1)]
+                    ).reshape(shape)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 70), (5, 9, 9), (3, 17, 130), (40, 37, 121),
+                                   (70, 20, 30), (2, 6, 11, 13)])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_sweep_parity(dev, shape, r):
+    x = torch.from_numpy(_vol(shape, 100 + r + len(shape))).to(dev)
+    flips = 0
+    cur = x
+    for _ in range(2):  # two sweeps, each teacher-forced
+        y, sel = osbf.forward3d(cur, r, 1, return_sel=True)
+        a = cur.cpu().numpy().reshape(-1, *shape[-3:])
+        b = y.cpu().numpy().reshape(-1, *shape[-3:])
+        s = sel[0].cpu().numpy().reshape(-1, *shape[-3:])
+        for v in range(a.shape[0]):
+            flips += check_sweep3d(a[v], b[v], r, s[v])
+        cur = y
+    assert flips <= max(2, int(0.001 * cur.numel())), f"{flips} value-changing near-tie flips"
+
+
+def test_multi_sweep_equals_chained_single_sweeps(dev):
+    """T sweeps in one call equal T single-sweep calls bit for bit (the
+    ping-pong through the workspace changes nothing), also in place."""
+    x = torch.from_numpy(_vol((30, 41, 67), 7)).to(dev)
+    y, sel = osbf.forward3d(x, 2, 4, return_sel=True)
+    cur = x
+    for t in range(4):
+        cur, s1 = osbf.forward3d(cur, 2, 1, return_sel=True)
+        assert torch.equal(s1[0], sel[t])
+    assert torch.equal(cur, y)
+    z = x.clone()
+    osbf.forward3d(z, 2, 3, out=z)
+    assert torch.equal(z, osbf.forward3d(x, 2, 3))
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_integer_selection_bit_exact(dev, r):
+    """Integer voxels 0..255: every FP32 window sum and scaled distance is an
+    exact integer, so the maps equal the oracle's exact int64 selection."""
+    rng = np.random.default_rng(200 + r)
+    vol = rng.integers(0, 256, size=(13, 19, 70))
+    y, sel = osbf.forward3d(torch.from_numpy(vol.astype(np.float32)).to(dev), r, 1, return_sel=True)
+    want_sel, sums = oracle.select_int64_3d(vol, r)
+    assert np.array_equal(sel[0].cpu().numpy(), want_sel)
+    n = np.where(np.arange(14) < 6, (r + 1) * (2 * r + 1) ** 2, (r + 1) ** 3)
+    mean = np.take_along_axis(sums, want_sel[..., None].astype(np.int64), 3)[..., 0] / n[want_sel]
+    np.testing.assert_allclose(y.cpu().numpy(), mean, rtol=0, atol=4e-5)  # FP32 near 255
+
+
+def test_fixed_points(dev):
+    """Constant volumes and two dyadic levels split by any plane are fixed
+    points of every sweep, bit for bit."""
+    D, H, W = 21, 33, 70
+    c = torch.full((D, H, W), 0.375, device=dev)
+    assert torch.equal(osbf.forward3d(c, 3, 3), c)
+    rng = np.random.default_rng(3)
+    z, y, x = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
+    for _ in range(3):
+        nrm = rng.normal(size=3)
+        p0 = rng.uniform([0, 0, 0], [W, H, D])
+        vol = np.where(nrm[0] * x + nrm[1] * y + nrm[2] * z < nrm @ p0, 0.25, 0.75).astype(np.float32)
+        t = torch.from_numpy(vol).to(dev)
+        for r in (1, 2, 4):
+            assert torch.equal(osbf.forward3d(t, r, 2), t)
+
+
+def test_identity_and_errors(dev):
+    x = torch.rand(4, 5, 6, device=dev)
+    assert torch.equal(osbf.forward3d(x, 0, 3), x)
+    assert torch.equal(osbf.forward3d(x, 2, 0), x)
+    _, sel = osbf.forward3d(x, 0, 2, return_sel=True)
+    assert int(sel.max()) == 0
+    with pytest.raises(osbf.OsbfError) as ei:
+        osbf.forward3d(x, 5, 1)
+    assert ei.value.status == 2
+    with pytest.raises(osbf.OsbfError) as ei:
+        osbf.forward3d(x, -1, 1)
+    assert ei.value.status == 1
+
+
+def test_full_size_sampled(dev):
+    """256^3 volume (the benchmark's), r=2: one sweep checked teacher-forced on
+    sampled 12^3 crops (the oracle runs on the crop grown by r, clipped to the
+    volume, which holds every voxel the crop's windows read), then ten sweeps
+    keep the maximum principle and valid maps."""
+    r = 2
+    x = torch.from_numpy(synth.workload_volume()).to(dev)
+    y, sel = osbf.forward3d(x, r, 1, return_sel=True)
+    xn = x.cpu().numpy()
+    yn = y.cpu().numpy()
+    sn = sel[0].cpu().numpy()
+    D, H, W = xn.shape
+    n = 12
+    for z0, y0, x0 in [(0, 0, 0), (122, 130, 77), (244, 244, 244), (0, 100, 244), (200, 0, 3)]:
+        za, zb = max(0, z0 - r), min(D, z0 + n + r)
+        ya, yb = max(0, y0 - r), min(H, y0 + n + r)
+        xa, xb = max(0, x0 - r), min(W, x0 + n + r)
+        sub = xn[za:zb, ya:yb, xa:xb]
+        core = (slice(z0 - za, z0 - za + n), slice(y0 - ya, y0 - ya + n), slice(x0 - xa, x0 - xa + n))
+        _, sel_o, err, means = oracle.sweep3d(sub, r, return_means=True)
+        s = sn[z0:z0 + n, y0:y0 + n, x0:x0 + n].astype(np.int64)
+        e = err[core]
+        gap = np.take_along_axis(e, s[..., None], 3)[..., 0] - e.min(axis=3)
+        assert gap.max() <= tau3(r, sub)
+        want = np.take_along_axis(means[core], s[..., None], 3)[..., 0]
+        assert np.abs(yn[z0:z0 + n, y0:y0 + n, x0:x0 + n] - want).max() <= 1e-5
+    y10, sel10 = osbf.forward3d(x, r, 10, return_sel=True)
+    assert float(y10.min()) >= float(x.min()) and float(y10.max()) <= float(x.max())
+    assert int(sel10.max()) <= 13
