@@ -17,6 +17,8 @@ plain FP32 forward on the same workload:
             selection maps + backward, and with a checkpoint every 5 sweeps
   variants  the bench workload through the fast approximation (Alg. 3) and
             the classical box filter, the paper's two timing comparisons
+  volume    a 256^3 FP32 volume (3D Voronoi K=64, sigma 0.05) through the
+            14-window volume filter, r in {1,2,3}, T=10
 
 Prints one JSON line (see the repository's benchmark contract).  Inputs are
 resident in HBM before every timed region; each timed region is bracketed by
@@ -44,23 +46,33 @@ H = W = 2048
 C = 3
 
 
+# sources that define the planar forward kernel (its launch shape is checked
+# separately through the plans)
+FWD_KERNEL_SOURCES = ("osbf_device.h", "osbf_fwd_device.h", "osbf_forward.hip")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2108_05021_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
+    for name in FWD_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2108_05021_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(config_key: str):
+def plan_signature(plans) -> dict:
+    return {str(r): [p["tile"][0], p["tile"][1], p["fused"]] for r, p in sorted(plans.items())}
+
+
+def measured_traffic(config_key: str, plans):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
+    was taken on the current forward kernel sources with the same launch
+    plans (else None)."""
     path = os.path.join(ROOT, "profiles", "fwd_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_hash") != kernel_source_hash():
+    if d.get("kernel_hash") != kernel_source_hash() or d.get("plans") != plan_signature(plans):
         return None
     return d.get("per_launch_bytes", {}).get(config_key)
 
@@ -198,11 +210,29 @@ def form_fwd_bwd(reps):
         return osbf.backward(w, r, T, ckpt=ck, ck=5)
     t_maps = _timed(maps, reps)
     t_ck = _timed(ckpt, reps)
+    _, sel = osbf.forward(x, r, T, return_sel=True)
+    t_adj = _timed(lambda: osbf.backward(w, r, T, sel=sel), reps)
     return {"workload": "32x3x512x512 Voronoi K=64 + N(0,0.05^2), r=3, T=10, loss sum(W*U), W~N(0,1)",
             "plain_fp32_forward_mpix_it_s": round(pxit / t_fwd / 1e6, 1),
             "maps_u8": {"mpix_it_s": round(pxit / t_maps / 1e6, 1), "vs_plain_fwd": round(t_fwd / t_maps, 3),
                         "map_bytes": T * x.numel()},
-            "ckpt_every_5": {"mpix_it_s": round(pxit / t_ck / 1e6, 1), "vs_plain_fwd": round(t_fwd / t_ck, 3)}}
+            "ckpt_every_5": {"mpix_it_s": round(pxit / t_ck / 1e6, 1), "vs_plain_fwd": round(t_fwd / t_ck, 3)},
+            "adjoint_only": {"mpix_it_s": round(pxit / t_adj / 1e6, 1),
+                             "achieved_GBs": round(9 * pxit / t_adj / 1e9, 1), "bytes_per_px_sweep": 9}}
+
+
+def form_volume(reps):
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    x = torch.from_numpy(synth.workload_volume()).cuda()
+    T = 10
+    res = {"workload": "256^3 f32 volume, 3D Voronoi K=64 + N(0,0.05^2), T=10, 14 windows "
+                       "(6 halves, 8 octants), replicate boundary"}
+    for r in (1, 2, 3):
+        t = _timed(lambda: osbf.forward3d(x, r, T), reps)
+        res[f"r{r}"] = {"mvox_it_s": round(x.numel() * T / t / 1e6, 1),
+                        "achieved_GBs": round(BYTES_PER_PX_SWEEP * x.numel() * T / t / 1e9, 1)}
+    return res
 
 
 def form_variants(reps):
@@ -301,7 +331,7 @@ def main():
         tot_bytes += BYTES_PER_PX_SWEEP * C * H * W * T_SWEEPS
         tot_ms += per_r_ms[r]
     achieved = tot_bytes / (tot_ms / 1e3) / 1e9
-    traffic = measured_traffic("rgb2048_T30")
+    traffic = measured_traffic("rgb2048_T30", plans)
 
     line = {
         "metric": "megapixel-iterations/s (fwd, batched, fwd+bwd) and % of HBM peak",
@@ -321,7 +351,7 @@ def main():
                    "planes": C, "height": H, "width": W, "radii": list(RADII), "iterations": T_SWEEPS},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "osbf::fwd_tile_kernel", "kernels": kernels,
+                     "kernel": "osbf::fwd_fixed_kernel", "kernels": kernels,
                      "bytes_per_px_sweep": BYTES_PER_PX_SWEEP},
     }
     if not args.no_cpu_baseline:
@@ -333,7 +363,8 @@ def main():
         line["forms"] = {"batched": form_batched(reps),
                          "precision": form_precision(reps, errors=not args.no_errors),
                          "fwd_bwd": form_fwd_bwd(reps),
-                         "variants": form_variants(reps)}
+                         "variants": form_variants(reps),
+                         "volume": form_volume(reps)}
     print(json.dumps(line), flush=True)
 
 

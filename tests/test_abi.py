@@ -121,3 +121,24 @@ def test_batched_rejects_bad_lists(lib):
     assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 1          # empty plane
     imgs[0].height = 8
     assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 3          # workspace missing
+
+
+def test_volume_entry_validation(lib):
+    """osbf3d_forward checks its arguments before touching the device."""
+    bad = ctypes.c_size_t(-1).value
+    assert lib.osbf3d_forward_workspace_size(2, 8, 9, 10, 3, 4) == 2 * 8 * 9 * 10 * 4
+    assert lib.osbf3d_forward_workspace_size(2, 8, 9, 10, 0, 4) == 0
+    assert lib.osbf3d_forward_workspace_size(2, 8, 9, 10, 3, 0) == 0
+    assert lib.osbf3d_forward_workspace_size(0, 8, 9, 10, 3, 4) == bad
+    assert lib.osbf3d_forward_workspace_size(1, 8, 9, 10, 5, 4) == bad
+    fake = ctypes.c_void_p(0x1000)
+    f = lib.osbf3d_forward
+    assert f(fake, fake, 0, 8, 8, 8, 2, 1, None, None, 0, None) == 1      # no volume
+    assert f(fake, fake, 1, 8, 0, 8, 2, 1, None, None, 0, None) == 1      # empty slice
+    assert f(fake, fake, 1, 8, 8, 8, -1, 1, None, None, 0, None) == 1     # negative radius
+    assert f(fake, fake, 1, 8, 8, 8, 5, 1, None, None, 0, None) == 2      # radius without kernel
+    assert f(fake, fake, 1, 8, 8, 8, 2, -1, None, None, 0, None) == 1     # negative T
+    assert f(None, fake, 1, 8, 8, 8, 2, 1, None, None, 0, None) == 1      # null source
+    assert f(fake, ctypes.c_void_p(0x2000), 1, 8, 8, 8, 2, 2, None, None, 0, None) == 3  # ping-pong needs ws
+    assert f(fake, fake, 1, 8, 8, 8, 2, 1, None, None, 0, None) == 3      # in place needs ws
+    assert lib.osbf_last_error()
