@@ -24,6 +24,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "osbf_oracle.c")
 _SRC3 = os.path.join(_HERE, "osbf3d_oracle.c")
+_SRCG = os.path.join(_HERE, "osbf_gauss_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libosbf_oracle.so")
 
 WINDOWS = ("R", "L", "D", "U", "SE", "SW", "NE", "NW")
@@ -36,7 +37,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-               "-o", tmp, _SRC, _SRC3, "-lm"]
+               "-o", tmp, _SRC, _SRC3, _SRCG, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -46,8 +47,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
-                                                                          os.path.getmtime(_SRC3)):
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+            os.path.getmtime(f) for f in (_SRC, _SRC3, _SRCG)):
         build(force=True)
     lib = ctypes.CDLL(_LIB_PATH)
     d = ctypes.POINTER(ctypes.c_double)
@@ -84,6 +85,11 @@ def _load():
     lib.oracle3d_forward.restype = ci
     lib.oracle3d_select_int64.argtypes = [i64, u8, i64, ci, ci, ci, ci]
     lib.oracle3d_select_int64.restype = None
+    cd = ctypes.c_double
+    lib.oracle_gauss_sweep.argtypes = [d, d, u8, d, d, ci, ci, ci, cd, ci]
+    lib.oracle_gauss_sweep.restype = None
+    lib.oracle_gauss_forward.argtypes = [d, d, u8, ci, ci, ci, ci, cd, ci, ci]
+    lib.oracle_gauss_forward.restype = ci
     _lib = lib
     return lib
 
@@ -294,3 +300,33 @@ def select_int64_3d(x, r: int):
     _load().oracle3d_select_int64(a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _pu8(sel),
                                   sums.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), D, H, W, r)
     return sel, sums
+
+
+# --------------------------------------------------- one-sided Gaussian
+
+def gauss_forward(x, r: int, sigma: float, T: int, *, return_sel: bool = False, nthreads: int = 0):
+    """T sweeps of the one-sided Gaussian filter (same windows and order as
+    the box filter, weights exp(-u^2/(2 sigma^2)) per axis), clamp boundary."""
+    shape = np.shape(x)
+    a = _planes(x)
+    P, H, W = a.shape
+    out = np.empty_like(a)
+    sel = np.empty((T, P, H, W), np.uint8) if return_sel else None
+    if _load().oracle_gauss_forward(_pd(a), _pd(out), _pu8(sel), P, H, W, r, float(sigma), T, nthreads) != 0:
+        raise ValueError("oracle_gauss_forward failed")
+    out = out.reshape(shape)
+    return (out, sel) if return_sel else out
+
+
+def gauss_sweep(u, r: int, sigma: float, *, nthreads: int = 0):
+    """One Gaussian sweep on one plane: (next, sel [H,W], err [H,W,8] =
+    N |mean_i - c| with N = Zh^2 Zf, means [H,W,8])."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    H, W = u.shape
+    out = np.empty_like(u)
+    sel = np.empty((H, W), np.uint8)
+    err = np.empty((H, W, 8), np.float64)
+    means = np.empty((H, W, 8), np.float64)
+    _load().oracle_gauss_sweep(_pd(u), _pd(out), _pu8(sel), _pd(err), _pd(means), H, W, r, float(sigma),
+                               nthreads)
+    return out, sel, err, means
