@@ -52,6 +52,7 @@ extern "C" {
 #define OSBF_ABI_VERSION 1
 #define OSBF_MAX_RADIUS 32          /* largest supported r */
 #define OSBF3D_MAX_RADIUS 4         /* largest r of the volume filter */
+#define OSBF_GAUSS_MAX_RADIUS 8     /* largest r of the one-sided Gaussian filter */
 
 typedef enum {
     OSBF_SUCCESS = 0,
@@ -265,6 +266,38 @@ size_t osbf3d_forward_workspace_size(int32_t volumes, int32_t depth, int32_t hei
 osbf_status osbf3d_forward(const float *src, float *dst, int32_t volumes, int32_t depth,
                            int32_t height, int32_t width, int32_t radius, int32_t iterations,
                            uint8_t *sel, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One-sided Gaussian filter (Sec. II-B, separable kernels).  The eight
+ * windows, their order and the selection rule are those of osbf_forward; a
+ * window's weight at offset (a, b) from the pixel is g(a) g(b) with
+ * g(u) = exp(-u^2 / (2 sigma^2)), and its mean is normalised by its own
+ * weight total: Zh^2 for quadrants, Zh Zf for halves, Zh = sum_{u=0..r} g(u)
+ * and Zf = 2 Zh - 1 (both one-sided parts contain the centre tap, as the
+ * box windows do).  sigma = +infinity gives the one-sided box filter.
+ */
+
+/* Workspace bytes osbf_gaussian_forward needs (0 if none), (size_t)-1 if invalid. */
+size_t osbf_gaussian_workspace_size(int32_t planes, int32_t height, int32_t width, int32_t radius,
+                                    int32_t iterations);
+
+/*
+ * osbf_gaussian_forward -- T sweeps of the one-sided Gaussian filter on FP32
+ * planes.
+ *   src, dst   device, [planes][height][width] contiguous FP32; may alias
+ *   radius     0..OSBF_GAUSS_MAX_RADIUS (0 or iterations = 0: copy); larger
+ *              radii return OSBF_ERROR_UNSUPPORTED (the sums are O(r))
+ *   sigma      > 0, +infinity allowed; NaN or <= 0 is OSBF_ERROR_INVALID_VALUE
+ *   sel        nullable device [iterations][planes][height][width] uint8
+ *              window indices (osbf_window) of every sweep
+ *   ws         device workspace of osbf_gaussian_workspace_size bytes (one
+ *              FP32 plane set; needed when iterations >= 2 or in place)
+ * Replicate boundary at every sweep; stream-ordered and asynchronous;
+ * arguments are checked before any launch.  FP32 arithmetic.
+ */
+osbf_status osbf_gaussian_forward(const float *src, float *dst, int32_t planes, int32_t height,
+                                  int32_t width, int32_t radius, float sigma, int32_t iterations,
+                                  uint8_t *sel, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

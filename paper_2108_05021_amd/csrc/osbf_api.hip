@@ -4,6 +4,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -767,6 +768,75 @@ osbf_status osbf3d_forward(const float *src, float *dst, int32_t vols, int32_t D
         a.dst = out;
         a.sel = sel ? sel + (size_t)t * nvox : nullptr;
         if ((e = launch_forward3d(a, stream)) != hipSuccess) return hip_fail(e, "volume launch");
+        cur = out;
+    }
+    return OSBF_SUCCESS;
+}
+
+
+size_t osbf_gaussian_workspace_size(int32_t planes, int32_t H, int32_t W, int32_t r, int32_t T) {
+    if (planes < 1 || H < 1 || W < 1 || r < 0 || r > OSBF_GAUSS_MAX_RADIUS || T < 0) return (size_t)-1;
+    if (T == 0 || r == 0) return 0;
+    return (size_t)planes * H * W * sizeof(float);
+}
+
+osbf_status osbf_gaussian_forward(const float *src, float *dst, int32_t planes, int32_t H, int32_t W,
+                                  int32_t r, float sigma, int32_t T, uint8_t *sel, void *ws,
+                                  size_t ws_bytes, void *stream_) {
+    g_last_error.clear();
+    osbf_status st = check_sizes(planes, H, W, OSBF_F32, std::min(r, (int32_t)OSBF_MAX_RADIUS), T);
+    if (st != OSBF_SUCCESS) return st;
+    if (r > OSBF_GAUSS_MAX_RADIUS)
+        return fail(OSBF_ERROR_UNSUPPORTED, "Gaussian radius %d above %d", r, OSBF_GAUSS_MAX_RADIUS);
+    if (!(sigma > 0.0f)) return fail(OSBF_ERROR_INVALID_VALUE, "sigma must be > 0 (got %g)", (double)sigma);
+    if (!src || !dst) return fail(OSBF_ERROR_INVALID_VALUE, "src and dst must be non-NULL");
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t n = (size_t)planes * H * W;
+    const size_t bytes = n * sizeof(float);
+    hipError_t e;
+    if (T == 0 || r == 0) {
+        if (src != dst && (e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy");
+        if (sel && T > 0 && (e = hipMemsetAsync(sel, OSBF_WIN_R, (size_t)T * n, stream)) != hipSuccess)
+            return hip_fail(e, "memset sel");
+        return OSBF_SUCCESS;
+    }
+    if ((T >= 2 || src == dst) && (!ws || ws_bytes < bytes))
+        return fail(OSBF_ERROR_WORKSPACE, "workspace of %zu bytes required, got %zu", bytes, ws ? ws_bytes : 0);
+
+    GaussLaunch a;
+    a.planes = planes; a.H = H; a.W = W; a.r = r;
+    gauss_tile(r, &a.tw, &a.th);
+    a.tiles_x = (W + a.tw - 1) / a.tw;
+    a.tiles_y = (H + a.th - 1) / a.th;
+    if ((long long)a.tiles_x * a.tiles_y * planes >= (1LL << 31))
+        return fail(OSBF_ERROR_INVALID_VALUE, "too many tiles");
+    // taps g(u) = exp(-u^2 / (2 sigma^2)) (1 for sigma = infinity); the
+    // normalisers come from the FP32 taps the kernel uses
+    double zh = 0.0;
+    for (int u = 0; u <= OSBF_GAUSS_MAX_R; ++u) {
+        const double gu = std::isinf(sigma) ? 1.0 : std::exp(-(double)u * u / (2.0 * (double)sigma * sigma));
+        a.g[u] = u <= r ? (float)gu : 0.0f;
+        if (u <= r) zh += (double)a.g[u];
+    }
+    const double zf = 2.0 * zh - 1.0;
+    a.w_q = (float)zf;
+    a.w_h = (float)zh;
+    a.N = (float)(zh * zh * zf);
+    a.invN = (float)(1.0 / (zh * zh * zf));
+
+    const float *cur = src;
+    if (src == dst && (T % 2) == 1) {
+        if ((e = hipMemcpyAsync(ws, src, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy to workspace");
+        cur = (const float *)ws;
+    }
+    for (int t = 0; t < T; ++t) {
+        float *out = ((T - 1 - t) % 2 == 0) ? dst : (float *)ws;
+        a.src = cur;
+        a.dst = out;
+        a.sel = sel ? sel + (size_t)t * n : nullptr;
+        if ((e = launch_gauss(a, stream)) != hipSuccess) return hip_fail(e, "Gaussian launch");
         cur = out;
     }
     return OSBF_SUCCESS;

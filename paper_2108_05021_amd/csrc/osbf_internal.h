@@ -70,4 +70,19 @@ void fwd3d_geometry(int r, int *tw, int *th);
 size_t fwd3d_lds_bytes(int r);
 hipError_t launch_forward3d(const Fwd3dLaunch &a, hipStream_t s);
 
+// One sweep of the one-sided Gaussian filter over every plane.
+#define OSBF_GAUSS_MAX_R 8
+struct GaussLaunch {
+    const float *src;     // [planes][H][W]
+    float *dst;           // [planes][H][W], never aliases src
+    uint8_t *sel;         // nullable [planes][H][W] map of this sweep
+    int planes, H, W, r;
+    int tw, th, tiles_x, tiles_y;
+    float g[OSBF_GAUSS_MAX_R + 1];  // taps g(0..r), g(0) = 1
+    float w_q, w_h, N, invN;        // distance weights: Zf, Zh, Zh^2 Zf, 1/N
+};
+bool gauss_radius(int r);
+void gauss_tile(int r, int *tw, int *th);
+hipError_t launch_gauss(const GaussLaunch &a, hipStream_t s);
+
 }  // namespace osbf

@@ -88,6 +88,10 @@ def lib():
     L.osbf3d_forward_workspace_size.restype = sz
     L.osbf3d_forward.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, sz, vp]
     L.osbf3d_forward.restype = ctypes.c_int
+    L.osbf_gaussian_workspace_size.argtypes = [i32, i32, i32, i32, i32]
+    L.osbf_gaussian_workspace_size.restype = sz
+    L.osbf_gaussian_forward.argtypes = [vp, vp, i32, i32, i32, i32, ctypes.c_float, i32, vp, vp, sz, vp]
+    L.osbf_gaussian_forward.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -307,4 +311,22 @@ def forward3d(x: torch.Tensor, r: int, T: int, *, return_sel: bool = False,
     ws = torch.empty(max(n, 1), dtype=torch.uint8, device=x.device) if n else None
     _check(lib().osbf3d_forward(_ptr(x), _ptr(y), vols, D, H, W, r, T, _ptr(sel), _ptr(ws),
                                 0 if ws is None else ws.numel(), _stream(x.device)))
+    return (y, sel) if return_sel else y
+
+
+def gaussian_forward(x: torch.Tensor, r: int, sigma: float, T: int, *, return_sel: bool = False,
+                     out: torch.Tensor | None = None):
+    """T sweeps of the one-sided Gaussian filter (weights exp(-u^2/(2 sigma^2))
+    per axis, the box filter's eight windows) on a (..., H, W) FP32 tensor."""
+    if x.dtype != torch.float32:
+        raise ValueError("expected a float32 tensor")
+    planes, H, W = _geometry(x)
+    y = torch.empty_like(x) if out is None else out
+    sel = torch.empty((T, *x.shape), dtype=torch.uint8, device=x.device) if return_sel else None
+    n = int(lib().osbf_gaussian_workspace_size(planes, H, W, r, T))
+    if n == (1 << 64) - 1:
+        n = 0  # invalid arguments: the entry point reports the error
+    ws = torch.empty(max(n, 1), dtype=torch.uint8, device=x.device) if n else None
+    _check(lib().osbf_gaussian_forward(_ptr(x), _ptr(y), planes, H, W, r, float(sigma), T, _ptr(sel),
+                                       _ptr(ws), 0 if ws is None else ws.numel(), _stream(x.device)))
     return (y, sel) if return_sel else y

@@ -142,3 +142,19 @@ def test_volume_entry_validation(lib):
     assert f(fake, ctypes.c_void_p(0x2000), 1, 8, 8, 8, 2, 2, None, None, 0, None) == 3  # ping-pong needs ws
     assert f(fake, fake, 1, 8, 8, 8, 2, 1, None, None, 0, None) == 3      # in place needs ws
     assert lib.osbf_last_error()
+
+
+def test_gaussian_entry_validation(lib):
+    """osbf_gaussian_forward checks its arguments before touching the device."""
+    bad = ctypes.c_size_t(-1).value
+    assert lib.osbf_gaussian_workspace_size(2, 9, 10, 3, 4) == 2 * 9 * 10 * 4
+    assert lib.osbf_gaussian_workspace_size(2, 9, 10, 0, 4) == 0
+    assert lib.osbf_gaussian_workspace_size(2, 9, 10, 9, 4) == bad
+    fake = ctypes.c_void_p(0x1000)
+    f = lib.osbf_gaussian_forward
+    assert f(fake, fake, 1, 8, 8, 9, 1.0, 1, None, None, 0, None) == 2        # radius without kernel
+    assert f(fake, fake, 1, 8, 8, 2, 0.0, 1, None, None, 0, None) == 1        # sigma <= 0
+    assert f(fake, fake, 1, 8, 8, 2, float("nan"), 1, None, None, 0, None) == 1
+    assert f(fake, fake, 0, 8, 8, 2, 1.0, 1, None, None, 0, None) == 1        # no plane
+    assert f(fake, ctypes.c_void_p(0x2000), 1, 8, 8, 2, 1.0, 2, None, None, 0, None) == 3  # needs ws
+    assert lib.osbf_last_error()
