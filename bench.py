@@ -19,6 +19,8 @@ plain FP32 forward on the same workload:
             the classical box filter, the paper's two timing comparisons
   volume    a 256^3 FP32 volume (3D Voronoi K=64, sigma 0.05) through the
             14-window volume filter, r in {1,2,3}, T=10
+  gaussian  the bench image through the one-sided Gaussian filter (Sec. II-B),
+            r in {2,5,8} with sigma = r/2, T=10, next to the box filter
 
 Prints one JSON line (see the repository's benchmark contract).  Inputs are
 resident in HBM before every timed region; each timed region is bracketed by
@@ -221,6 +223,21 @@ def form_fwd_bwd(reps):
                              "achieved_GBs": round(9 * pxit / t_adj / 1e9, 1), "bytes_per_px_sweep": 9}}
 
 
+def form_gaussian(reps):
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    x = torch.from_numpy(synth.workload_rgb()).cuda()
+    T = 10
+    res = {"workload": "3x2048x2048 f32 (the bench image), T=10, sigma = r/2, replicate boundary"}
+    for r in (2, 5, 8):
+        tg = _timed(lambda: osbf.gaussian_forward(x, r, r / 2.0, T), reps)
+        tb = _timed(lambda: osbf.forward(x, r, T), reps)
+        res[f"r{r}"] = {"mpix_it_s": round(x.numel() * T / tg / 1e6, 1),
+                        "box_filter_mpix_it_s": round(x.numel() * T / tb / 1e6, 1),
+                        "time_over_box_filter": round(tg / tb, 3)}
+    return res
+
+
 def form_volume(reps):
     import torch
     from paper_2108_05021_amd import osbf, synth
@@ -364,7 +381,8 @@ def main():
                          "precision": form_precision(reps, errors=not args.no_errors),
                          "fwd_bwd": form_fwd_bwd(reps),
                          "variants": form_variants(reps),
-                         "volume": form_volume(reps)}
+                         "volume": form_volume(reps),
+                         "gaussian": form_gaussian(reps)}
     print(json.dumps(line), flush=True)
 
 
