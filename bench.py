@@ -21,6 +21,8 @@ plain FP32 forward on the same workload:
             14-window volume filter, r in {1,2,3}, T=10
   gaussian  the bench image through the one-sided Gaussian filter (Sec. II-B),
             r in {2,5,8} with sigma = r/2, T=10, next to the box filter
+  autotune  the bench workload with the plans osbf_autotune measures on this
+            device, next to the measured table the timed step uses
 
 Prints one JSON line (see the repository's benchmark contract).  Inputs are
 resident in HBM before every timed region; each timed region is bracketed by
@@ -238,6 +240,28 @@ def form_gaussian(reps):
     return res
 
 
+def form_autotune(reps):
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    x = torch.from_numpy(synth.workload_rgb()).cuda()
+    res = {"workload": "the bench workload (3x2048x2048 f32, T=30)"}
+    osbf.autotune_clear()
+    for r in RADII:
+        table = osbf.forward_plan(C, H, W, torch.float32, r, T_SWEEPS)
+        t_table = _timed(lambda: osbf.forward(x, r, T_SWEEPS), reps)
+        t0 = time.perf_counter()
+        tuned = osbf.autotune(x, r, T_SWEEPS)
+        tune_s = time.perf_counter() - t0
+        t_tuned = _timed(lambda: osbf.forward(x, r, T_SWEEPS), reps)
+        res[f"r{r}"] = {"table_plan": {"tile": list(table["tile"]), "fused": table["fused"]},
+                        "table_mpix_it_s": round(x.numel() * T_SWEEPS / t_table / 1e6, 1),
+                        "tuned_plan": {"tile": list(tuned["tile"]), "fused": tuned["fused"]},
+                        "tuned_mpix_it_s": round(x.numel() * T_SWEEPS / t_tuned / 1e6, 1),
+                        "tuning_s": round(tune_s, 3)}
+    osbf.autotune_clear()
+    return res
+
+
 def form_volume(reps):
     import torch
     from paper_2108_05021_amd import osbf, synth
@@ -382,7 +406,8 @@ def main():
                          "fwd_bwd": form_fwd_bwd(reps),
                          "variants": form_variants(reps),
                          "volume": form_volume(reps),
-                         "gaussian": form_gaussian(reps)}
+                         "gaussian": form_gaussian(reps),
+                         "autotune": form_autotune(reps)}
     print(json.dumps(line), flush=True)
 
 

@@ -229,6 +229,28 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osb
                               int32_t *launches);
 
 /*
+ * osbf_autotune -- measure the launch plans of osbf_forward for this problem
+ * and keep the fastest for the calling thread's device.
+ *   src, dst   distinct device buffers of [planes][height][width] elements of
+ *              dtype; src is read, dst is overwritten (scratch)
+ * Times every fixed LDS geometry and fusion depth that fits (and the cost
+ * model's generic plan) with HIP events, a few launches each, on `stream`,
+ * and blocks until done (do not call during stream capture).  The winner is
+ * cached per (device, radius, dtype, size class: planes*height*width below or
+ * at least 2^20) and used by later osbf_forward / osbf_backward /
+ * osbf_forward_plan calls of that class; OSBF_PLAN in the environment still
+ * takes precedence.  Every plan computes the same bits, so tuning changes
+ * speed, never results.  Writes the chosen tile and fused sweeps (0 for
+ * radius 0 or iterations 0).  The cache is process state guarded by a mutex.
+ */
+osbf_status osbf_autotune(const void *src, void *dst, int32_t planes, int32_t height, int32_t width,
+                          osbf_dtype dtype, int32_t radius, int32_t iterations, void *stream,
+                          int32_t *tile_w, int32_t *tile_h, int32_t *fused);
+
+/* Forget every autotuned plan (later calls use the measured table again). */
+void osbf_autotune_clear(void);
+
+/*
  * Volume filter (Sec. "Higher Dimension Case").  The one-sided kernels along
  * x, y and z span 14 windows per voxel, every one containing the voxel:
  *   0 +x, 1 -x, 2 +y, 3 -y, 4 +z, 5 -z   halves: one axis [c, c+r] or

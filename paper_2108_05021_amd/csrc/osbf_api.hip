@@ -1,6 +1,8 @@
 // C ABI of the one-sided box filter: argument validation, launch planning and
 // the sweep driver.  All device work is enqueued on the caller's stream.
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 #include <algorithm>
@@ -115,9 +117,39 @@ const TunedShape kTuned[] = {{1, GEOM_64x48, 3}, {2, GEOM_64x48, 2}, {3, GEOM_64
                              {4, GEOM_64x60, 1}, {5, GEOM_64x60, 1}, {8, GEOM_64x48, 1},
                              {10, GEOM_64x60, 1}, {16, GEOM_128x64, 1}};
 
+// Autotune cache: (device, radius, dtype, size class) -> plan measured by
+// osbf_autotune.  Guarded by a mutex; every plan gives the same bits, so the
+// cache changes speed only.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, Plan> g_tune;
+
+int size_class(int planes, int H, int W) { return (long long)planes * H * W >= (1LL << 20) ? 1 : 0; }
+
+bool tuned_plan(int planes, int H, int W, int r, int T, int dtype, Plan *out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(dev, r, dtype, size_class(planes, H, W)));
+    if (it == g_tune.end()) return false;
+    const Plan &p = it->second;
+    if (p.k > std::min(T, 8)) return false;  // fewer sweeps than the tuned fusion
+    *out = p;
+    return true;
+}
+
+Plan choose_plan_model(int H, int W, int r, int T);
+
+// The launch plan: OSBF_PLAN if set, else an autotuned plan for this device
+// and problem class, else the measured table, else the cost model.
+Plan choose_plan(int planes, int H, int W, int r, int T, int dtype) {
+    Plan p;
+    if (!getenv("OSBF_PLAN") && tuned_plan(planes, H, W, r, T, dtype, &p)) return p;
+    return choose_plan_model(H, W, r, T);
+}
+
 // OSBF_PLAN="geom,k" forces a plan (tests and tuning): geom 0 is the generic
 // kernel (region chosen by cost), 1.. the fixed geometries (enum Geom).
-Plan choose_plan(int H, int W, int r, int T) {
+Plan choose_plan_model(int H, int W, int r, int T) {
     const size_t limit = lds_limit();
     const int kmax = T > 0 ? std::min(T, 8) : 1;
     int force_geom = -1, force_k = -1;
@@ -306,7 +338,7 @@ osbf_status forward_impl(const void *src, void *dst, int32_t planes, int32_t H, 
         return OSBF_SUCCESS;
     }
 
-    const Plan plan = choose_plan(H, W, r, T);
+    const Plan plan = choose_plan(planes, H, W, r, T, (int)dtype);
     if (!plan.tw)
         return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
     const std::vector<Launch> launches = make_launches(T, nck ? ck : 0, plan.k);
@@ -444,7 +476,7 @@ osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes,
     }
     // Checkpoint mode: recompute each segment's maps with the forward's own
     // launches (bit-identical maps), then run that segment's adjoints.
-    const Plan plan = choose_plan(H, W, r, T);
+    const Plan plan = choose_plan(planes, H, W, r, T, OSBF_F32);
     if (!plan.tw) return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
     const std::vector<Launch> launches = make_launches(T, ck, plan.k);
     const int nseg = (T + ck - 1) / ck;
@@ -479,7 +511,7 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t H, int32_t W, osbf_dtype d
         *tile_w = *tile_h = *fused = *launches = 0;
         return OSBF_SUCCESS;
     }
-    const Plan plan = choose_plan(H, W, r, T);
+    const Plan plan = choose_plan(planes, H, W, r, T, (int)dtype);
     if (!plan.tw)
         return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
     *tile_w = plan.tw;
@@ -840,6 +872,90 @@ osbf_status osbf_gaussian_forward(const float *src, float *dst, int32_t planes, 
         cur = out;
     }
     return OSBF_SUCCESS;
+}
+
+
+osbf_status osbf_autotune(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
+                          osbf_dtype dtype, int32_t r, int32_t T, void *stream_, int32_t *tile_w,
+                          int32_t *tile_h, int32_t *fused) {
+    g_last_error.clear();
+    osbf_status st = check_sizes(planes, H, W, dtype, r, T);
+    if (st != OSBF_SUCCESS) return st;
+    if (!src || !dst || src == dst)
+        return fail(OSBF_ERROR_INVALID_VALUE, "src and dst must be distinct non-NULL buffers");
+    if (!tile_w || !tile_h || !fused) return fail(OSBF_ERROR_INVALID_VALUE, "output pointers must be non-NULL");
+    *tile_w = *tile_h = *fused = 0;
+    if (T == 0 || r == 0) return OSBF_SUCCESS;
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t limit = lds_limit();
+    const int kmax = std::min(T, 6);
+    // candidates: every fixed geometry and fusion depth that fits, and the
+    // cost model's generic choice
+    std::vector<Plan> cands;
+    if (fixed_radius(r))
+        for (int g = 1; g < NUM_GEOMS; ++g)
+            for (int k = 1; k <= kmax; ++k) {
+                const Plan p = make_plan(g, kGeomDims[g][0], kGeomDims[g][1], r, k);
+                if (p.tw && p.lds_bytes() <= limit) cands.push_back(p);
+            }
+    {
+        Plan best;
+        double best_cost = 1e300;
+        for (int k = 1; k <= kmax; ++k)
+            for (const auto &reg : kRegions) {
+                const Plan p = make_plan(GEOM_GENERIC, reg[0], reg[1], r, k);
+                if (!p.tw || p.lds_bytes() > limit) continue;
+                const double c = plan_cost(p, H, W, r);
+                if (c < best_cost) { best_cost = c; best = p; }
+            }
+        if (best.tw) cands.push_back(best);
+    }
+    if (cands.empty()) return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "event");
+    }
+    Plan best;
+    double best_ms = 1e300;
+    constexpr int kReps = 3;
+    for (const Plan &p : cands) {
+        // one warm-up launch, then kReps timed launches of k sweeps each
+        e = enqueue_forward(p, p.k, src, dst, nullptr, planes, H, W, r, dtype, stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, stream);
+        for (int i = 0; i < kReps && e == hipSuccess; ++i)
+            e = enqueue_forward(p, p.k, src, dst, nullptr, planes, H, W, r, dtype, stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return hip_fail(e, "autotune launch");
+        }
+        const double per_sweep = ms / (kReps * p.k);
+        if (per_sweep < best_ms) { best_ms = per_sweep; best = p; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "device");
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[std::make_tuple(dev, r, (int)dtype, size_class(planes, H, W))] = best;
+    }
+    *tile_w = best.tw;
+    *tile_h = best.th;
+    *fused = best.k;
+    return OSBF_SUCCESS;
+}
+
+void osbf_autotune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
 }
 
 }  // extern "C"

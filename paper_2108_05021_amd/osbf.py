@@ -92,6 +92,10 @@ def lib():
     L.osbf_gaussian_workspace_size.restype = sz
     L.osbf_gaussian_forward.argtypes = [vp, vp, i32, i32, i32, i32, ctypes.c_float, i32, vp, vp, sz, vp]
     L.osbf_gaussian_forward.restype = ctypes.c_int
+    L.osbf_autotune.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, vp] + [ctypes.POINTER(i32)] * 3
+    L.osbf_autotune.restype = ctypes.c_int
+    L.osbf_autotune_clear.argtypes = []
+    L.osbf_autotune_clear.restype = None
     _lib = L
     return L
 
@@ -330,3 +334,20 @@ def gaussian_forward(x: torch.Tensor, r: int, sigma: float, T: int, *, return_se
     _check(lib().osbf_gaussian_forward(_ptr(x), _ptr(y), planes, H, W, r, float(sigma), T, _ptr(sel),
                                        _ptr(ws), 0 if ws is None else ws.numel(), _stream(x.device)))
     return (y, sel) if return_sel else y
+
+
+def autotune(x: torch.Tensor, r: int, T: int) -> dict:
+    """Measure osbf_forward's launch plans on x's shape and dtype (x is read,
+    a scratch output is written) and keep the fastest for this device and
+    problem class; returns the chosen tile and fused sweeps.  Blocks."""
+    planes, H, W = _geometry(x)
+    scratch = torch.empty_like(x)
+    tw, th, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().osbf_autotune(_ptr(x), _ptr(scratch), planes, H, W, DTYPES[x.dtype], r, T,
+                               _stream(x.device), ctypes.byref(tw), ctypes.byref(th), ctypes.byref(k)))
+    return {"tile": (tw.value, th.value), "fused": k.value}
+
+
+def autotune_clear() -> None:
+    """Forget every autotuned plan."""
+    lib().osbf_autotune_clear()

@@ -158,3 +158,18 @@ def test_gaussian_entry_validation(lib):
     assert f(fake, fake, 0, 8, 8, 2, 1.0, 1, None, None, 0, None) == 1        # no plane
     assert f(fake, ctypes.c_void_p(0x2000), 1, 8, 8, 2, 1.0, 2, None, None, 0, None) == 3  # needs ws
     assert lib.osbf_last_error()
+
+
+def test_autotune_entry_validation(lib):
+    """osbf_autotune checks its arguments before touching the device."""
+    fake, other = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    out = [ctypes.c_int32(7) for _ in range(3)]
+    refs = [ctypes.byref(v) for v in out]
+    assert lib.osbf_autotune(fake, fake, 1, 8, 8, 0, 2, 3, None, *refs) == 1        # in place
+    assert lib.osbf_autotune(None, other, 1, 8, 8, 0, 2, 3, None, *refs) == 1       # null source
+    assert lib.osbf_autotune(fake, other, 0, 8, 8, 0, 2, 3, None, *refs) == 1       # no plane
+    assert lib.osbf_autotune(fake, other, 1, 8, 8, 9, 2, 3, None, *refs) == 1       # bad dtype
+    assert lib.osbf_autotune(fake, other, 1, 8, 8, 0, 2, 3, None, None, None, None) == 1
+    assert lib.osbf_autotune(fake, other, 1, 8, 8, 0, 0, 3, None, *refs) == 0       # r = 0: nothing to tune
+    assert [v.value for v in out] == [0, 0, 0]
+    lib.osbf_autotune_clear()
