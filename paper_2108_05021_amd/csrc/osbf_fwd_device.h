@@ -342,6 +342,70 @@ __device__ __forceinline__ void fixed_phase_v(const float *P, float *V, int lx, 
     }
 }
 
+// First sweep's phase A fused with the tile load: each lane loads, for every
+// block of R rows its wave owns, the block's 2R input rows of its column
+// straight from global memory (rows clamped into the image; all loads issued
+// before the first wait), forms V in registers, and writes the block's own P
+// and V rows to LDS.  No barrier is needed between load and phase A, and the
+// FP32 operations are those of fixed_phase_v.
+template <int DT, int R, int RW, int RH, int NT>
+__device__ __forceinline__ void fixed_load_phase_v(const typename Storage<DT>::T *src, float *P, float *V,
+                                                   int lx, int ly, int ox, int oy, int H, int W, int xa,
+                                                   int xb, int ya, int yb) {
+    using S = Storage<DT>;
+    constexpr int PITCH = RW + 1;
+    constexpr int NY = NT / RW;
+    constexpr int MB = ((RH - 1) / R + NY - 1) / NY;  // blocks per wave, at most
+    const int x = ox + lx;
+    if (x < max(0, xa - R) || x >= min(W, xb + R)) return;
+    const int yend = yb + R;
+    const int nblk = (yend - ya + R - 1) / R;
+    typename S::T raw[MB][2 * R];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int b = ly + i * NY;
+        if (b < nblk) {
+            const int y0 = ya + b * R;
+#pragma unroll
+            for (int t = 0; t < 2 * R; ++t) raw[i][t] = src[(size_t)min(max(y0 - R + t, 0), H - 1) * W + x];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int b = ly + i * NY;
+        if (b >= nblk) break;
+        const int y0 = ya + b * R;
+        float p[2 * R];
+#pragma unroll
+        for (int t = 0; t < 2 * R; ++t) p[t] = S::cvt(raw[i][t]);
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int y = y0 + t;
+            if (y < yend && y < H) P[(y - oy) * PITCH + lx] = p[R + t];
+        }
+        float *vc = V + (y0 - oy) * PITCH + lx;
+        float v = p[0];
+#pragma unroll
+        for (int t = 1; t <= R; ++t) v += p[t];
+        vc[0] = v;
+        if (y0 + R <= yend) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                v += p[R + t] - p[t - 1];
+                vc[t * PITCH] = v;
+            }
+        } else {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                if (y0 + t < yend) {
+                    v += p[R + t] - p[t - 1];
+                    vc[t * PITCH] = v;
+                }
+            }
+        }
+    }
+}
+
 // Phase B of the fixed-geometry kernel: Q on columns [xa, xb+R), rows
 // [ya, yb+R); H on the same columns, rows [ya, yb).  One lane per region row.
 template <int R, int RW, int RH, int NT, bool CL, int MODE = 0>
@@ -439,28 +503,6 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
     const bool interior = (X0 - ext >= 0) && (Y0 - ext >= 0) && (X0 + TW + ext <= W) &&
                           (Y0 + TH + ext <= H);
 
-    {   // clamped load of tile + halo: every row load of a thread is issued
-        // (from an in-bounds, clamped row) before the first wait; values are
-        // converted and written to LDS afterwards
-        constexpr int NL = (RH + NY - 1) / NY;
-        const int x = ox + lx;
-        const int y0 = max(0, oy), y1 = min(H, Y0 + TH + ext);
-        if (x >= 0 && x < W && lx < TW + 2 * ext) {
-            typename S::T raw[NL];
-#pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const int y = min(y0 + ly + i * NY, y1 - 1);
-                raw[i] = src[(size_t)y * W + x];
-            }
-#pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const int y = y0 + ly + i * NY;
-                if (y < y1) P[(y - oy) * PITCH + lx] = S::cvt(raw[i]);
-            }
-        }
-    }
-    __syncthreads();
-
     constexpr float fr1 = (float)(R + 1), f2r1 = (float)(2 * R + 1);
     constexpr float N = fr1 * fr1 * f2r1;
     const float invN = 1.0f / N;
@@ -471,15 +513,17 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
         const int xa = max(0, X0 - e), xb = min(W, X0 + TW + e);
         const int ya = max(0, Y0 - e), yb = min(H, Y0 + TH + e);
 
-        if (interior) {
+        if (j == 0)  // the load of the tile + halo, fused with the first phase A
+            fixed_load_phase_v<DT, R, RW, RH, NT>(src, P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
+        else if (interior)
             fixed_phase_v<R, RW, RH, NT, false>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
-            __syncthreads();
-            fixed_phase_qh<R, RW, RH, NT, false, MODE>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
-        } else {
+        else
             fixed_phase_v<R, RW, RH, NT, true>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
-            __syncthreads();
+        __syncthreads();
+        if (interior)
+            fixed_phase_qh<R, RW, RH, NT, false, MODE>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
+        else
             fixed_phase_qh<R, RW, RH, NT, true, MODE>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
-        }
         __syncthreads();
 
         // Phase C: selection and update on [xa, xb) x [ya, yb).
