@@ -114,7 +114,7 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 // off for r <= 3.
 struct TunedShape { int r, geom, k; };
 const TunedShape kTuned[] = {{1, GEOM_64x48, 3}, {2, GEOM_64x48, 2}, {3, GEOM_64x48, 2},
-                             {4, GEOM_64x60, 1}, {5, GEOM_64x60, 1}, {8, GEOM_64x48, 1},
+                             {4, GEOM_64x48, 1}, {5, GEOM_64x60, 1}, {8, GEOM_64x48, 1},
                              {10, GEOM_64x60, 1}, {16, GEOM_128x64, 1}};
 
 // Autotune cache: (device, radius, dtype, size class) -> plan measured by
