@@ -197,22 +197,24 @@ __global__ __launch_bounds__(256) void adjoint_kernel(BwdLaunch a) {
 
 // ---------------------------------------------------------------------------
 // Fixed-geometry adjoint for the common radii.  The LDS region is RW x RH
-// pixels (the tile grown by 2R on every side) with a compile-time pitch; the
-// selection lives in a byte array.  The vertical pass gives each lane one
-// region column and reads a block's 3R rows into registers once; the
-// horizontal pass spreads (row, column block) pairs over all lanes.  The
-// FP32 operations and their order are those of adjoint_kernel, so both
-// kernels give the same bits.
+// pixels (the tile grown by 2R on every side) with a compile-time pitch.  The
+// vertical pass gives each lane one region column: for every block of R rows
+// its wave owns, the lane loads the block's 3R rows of upstream gradient and
+// selection straight from global memory (all loads issued before the first
+// wait), forms gv and the masked running sums in registers and writes VL+VF,
+// VR+VF and VF to LDS.  The horizontal pass spreads (row, block) pairs over
+// all lanes and writes Gpad over VF (each block reads only its own VF
+// entries).  Three FP32 arrays, no selection array; the FP32 operations and
+// their order are those of adjoint_kernel, so both kernels give the same bits.
 template <int R, int RW, int RH, int NT>
 __global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
     extern __shared__ float lds[];
     constexpr int PITCH = RW + 1, ARR = RH * PITCH, NY = NT / RW;
+    constexpr int MB = ((RH - 1) / R + NY - 1) / NY;  // column blocks per wave, at most
     static_assert(RW == 64 && NT % 64 == 0, "one wave per region row");
-    float *const GV = lds;                 // gv, later Gpad
-    float *const HL = lds + ARR;
-    float *const HR = lds + 2 * ARR;
-    float *const VF = lds + 3 * ARR;
-    uint8_t *const SL = (uint8_t *)(lds + 4 * ARR);
+    float *const HL = lds;
+    float *const HR = lds + ARR;
+    float *const VF = lds + 2 * ARR;  // VF, then Gpad
     const int tid = threadIdx.x, lx = tid % RW;
     const int ly = __builtin_amdgcn_readfirstlane(tid / RW);
     const int H = a.H, W = a.W, TW = a.tw, TH = a.th;
@@ -229,75 +231,67 @@ __global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
     // F region it reads (q region grown by R)
     const int qx0 = X0 == 0 ? -R : X0, qx1 = X0 + TW >= W ? W + R : X0 + TW;
     const int qy0 = Y0 == 0 ? -R : Y0, qy1 = Y0 + TH >= H ? H + R : Y0 + TH;
-    const int gx0 = qx0 - R, gx1 = qx1 + R, gy0 = qy0 - R, gy1 = qy1 + R;
+    const int gx0 = qx0 - R, gx1 = qx1 + R;
     const float inv_h = 1.0f / (float)((R + 1) * (2 * R + 1));
     const float inv_q = 1.0f / (float)((R + 1) * (R + 1));
     const int x = ox + lx;
-    const bool xcol = x >= gx0 && x < gx1;
-
-    // Phase 0: gv and selection on the F region, zero outside the image.
-    // Every load of a lane is issued (clamped into the image) before the
-    // first wait.
-    if (xcol) {
-        constexpr int NL = (RH + NY - 1) / NY;
-        const bool xin = x >= 0 && x < W;
-        const int xc = min(max(x, 0), W - 1);
-        float graw[NL];
-        uint8_t sraw[NL];
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int y = min(max(min(gy0 + ly + i * NY, gy1 - 1), 0), H - 1);
-            graw[i] = gn[(size_t)y * W + xc];
-            sraw[i] = sl[(size_t)y * W + xc];
-        }
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int y = gy0 + ly + i * NY;
-            if (y < gy1) {
-                const int o = (y - oy) * PITCH + lx;
-                const bool in = xin && y >= 0 && y < H;
-                const int s = sraw[i];
-                GV[o] = in ? graw[i] * (s >= 4 ? inv_q : inv_h) : 0.f;
-                SL[o] = in ? sraw[i] : 0;
-            }
-        }
-    }
-    __syncthreads();
 
     // Phase A: per column of [qx0 - R, qx1 + R), VL+VF, VR+VF and VF on rows
-    // [qy0, qy1) in blocks of R rows anchored at multiples of R.
-    if (xcol) {
+    // [qy0, qy1) in blocks of R rows anchored at multiples of R; gv is
+    // G'(p)/n_m(p) inside the image and 0 outside.
+    if (x >= gx0 && x < gx1) {
+        const bool xin = x >= 0 && x < W;
+        const int xc = min(max(x, 0), W - 1);
         const int nblk = (qy1 - qy0 + R - 1) / R;
-        for (int b = ly; b < nblk; b += NY) {
+        float graw[MB][3 * R];
+        uint8_t sraw[MB][3 * R];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const int b = ly + i * NY;
+            if (b < nblk) {
+                const int y0 = qy0 + b * R;
+#pragma unroll
+                for (int j = 0; j < 3 * R; ++j) {  // rows y0-R .. y0+2R-1, clamped
+                    const size_t gi = (size_t)min(max(y0 - R + j, 0), H - 1) * W + xc;
+                    graw[i][j] = gn[gi];
+                    sraw[i][j] = sl[gi];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const int b = ly + i * NY;
+            if (b >= nblk) break;
             const int y0 = qy0 + b * R;
             const bool full = y0 + R <= qy1;
             float g[3 * R];
             int s[3 * R];
 #pragma unroll
-            for (int i = 0; i < 3 * R; ++i) {  // rows y0-R .. y0+2R-1
-                const int o = (min(y0 - R + i, gy1 - 1) - oy) * PITCH + lx;
-                g[i] = GV[o];
-                s[i] = SL[o];
+            for (int j = 0; j < 3 * R; ++j) {
+                const int yy = y0 - R + j;
+                const bool in = xin && yy >= 0 && yy < H;
+                s[j] = in ? sraw[i][j] : 0;
+                g[j] = in ? graw[i][j] * (s[j] >= 4 ? inv_q : inv_h) : 0.f;
             }
             float u1 = pick(M_C1, s[0], g[0]), u3 = pick(M_C3, s[0], g[0]), ud = pick(M_FD, s[0], g[0]);
 #pragma unroll
-            for (int i = 1; i <= R; ++i) {
-                u1 += pick(M_C1, s[i], g[i]);
-                u3 += pick(M_C3, s[i], g[i]);
-                ud += pick(M_FD, s[i], g[i]);
+            for (int j = 1; j <= R; ++j) {
+                u1 += pick(M_C1, s[j], g[j]);
+                u3 += pick(M_C3, s[j], g[j]);
+                ud += pick(M_FD, s[j], g[j]);
             }
             float d2 = pick(M_C2, s[R], g[R]), d4 = pick(M_C4, s[R], g[R]), du = pick(M_FU, s[R], g[R]);
 #pragma unroll
-            for (int i = R + 1; i <= 2 * R; ++i) {
-                d2 += pick(M_C2, s[i], g[i]);
-                d4 += pick(M_C4, s[i], g[i]);
-                du += pick(M_FU, s[i], g[i]);
+            for (int j = R + 1; j <= 2 * R; ++j) {
+                d2 += pick(M_C2, s[j], g[j]);
+                d4 += pick(M_C4, s[j], g[j]);
+                du += pick(M_FU, s[j], g[j]);
             }
             auto emit = [&](int tt) {
-                const int i = R + tt;
+                const int j = R + tt;
                 const float vf = ud + du;
-                const float vl = u1 + d2 - pick(M_FR, s[i], g[i]);
-                const float vr = u3 + d4 - pick(M_FL, s[i], g[i]);
+                const float vl = u1 + d2 - pick(M_FR, s[j], g[j]);
+                const float vr = u3 + d4 - pick(M_FL, s[j], g[j]);
                 const int o = (y0 + tt - oy) * PITCH + lx;
                 HL[o] = vl + vf;
                 HR[o] = vr + vf;
@@ -321,8 +315,8 @@ __global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
     }
     __syncthreads();
 
-    // Phase B: Gpad = Hl[HL] + Hr[HR] - VF on [qx0, qx1) x [qy0, qy1), into
-    // GV; work item = (row, block of R columns), rows fastest.
+    // Phase B: Gpad = Hl[HL] + Hr[HR] - VF on [qx0, qx1) x [qy0, qy1), over
+    // VF; work item = (row, block of R columns), rows fastest.
     {
         const int nrow = qy1 - qy0;
         const int nblk = (qx1 - qx0 + R - 1) / R;
@@ -342,13 +336,13 @@ __global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
             for (int i = 1; i <= R; ++i) sl_ += hl[i];
 #pragma unroll
             for (int i = 1; i <= R; ++i) sr_ += hr[i];
-            GV[ro + x0] = sl_ + sr_ - VF[ro + x0];
+            VF[ro + x0] = sl_ + sr_ - VF[ro + x0];
 #pragma unroll
             for (int tt = 1; tt < R; ++tt) {
                 if (x0 + tt < qx1) {
                     sl_ += hl[R + tt] - hl[tt - 1];
                     sr_ += hr[R + tt] - hr[tt - 1];
-                    GV[ro + x0 + tt] = sl_ + sr_ - VF[ro + x0 + tt];
+                    VF[ro + x0 + tt] = sl_ + sr_ - VF[ro + x0 + tt];
                 }
             }
             rr += dr;
@@ -362,6 +356,7 @@ __global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
     __syncthreads();
 
     // Phase C: fold the halo onto edge pixels (adjoint of the clamp), store.
+    const float *GP = VF;
     float *g = a.g + plane_off;
     const int xe = min(W, X0 + TW), ye = min(H, Y0 + TH);
     if (x >= X0 && x < xe) {
@@ -370,11 +365,11 @@ __global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
             const int ya = y == 0 ? -R : y, yb = y == H - 1 ? H - 1 + R : y;
             float acc;
             if (ya == yb && xa == xb) {
-                acc = GV[(y - oy) * PITCH + lx];
+                acc = GP[(y - oy) * PITCH + lx];
             } else {
                 acc = 0.f;
                 for (int qy = ya; qy <= yb; ++qy)
-                    for (int qx = xa; qx <= xb; ++qx) acc += GV[(qy - oy) * PITCH + (qx - ox)];
+                    for (int qx = xa; qx <= xb; ++qx) acc += GP[(qy - oy) * PITCH + (qx - ox)];
             }
             g[(size_t)y * W + x] = acc;
         }
@@ -391,7 +386,7 @@ static int adjoint_fixed_rows(int r) {
     }
 }
 
-size_t adjoint_fixed_lds_bytes(int rh) { return (size_t)rh * 65 * (4 * sizeof(float) + 1); }
+size_t adjoint_fixed_lds_bytes(int rh) { return (size_t)3 * rh * 65 * sizeof(float); }
 
 bool adjoint_fixed_tile(int r, int *tw, int *th) {
     const int rh = adjoint_fixed_rows(r);
