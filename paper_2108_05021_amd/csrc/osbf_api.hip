@@ -250,7 +250,8 @@ bool adjoint_tile(int r, BwdLaunch *b) {
     const char *env = getenv("OSBF_ADJOINT");
     const bool force_generic = env && strcmp(env, "generic") == 0;
     b->fixed = 0;
-    if (!force_generic && adjoint_fixed_tile(r, &b->tw, &b->th)) {
+    size_t fixed_lds = 0;
+    if (!force_generic && adjoint_fixed_tile(r, &b->tw, &b->th, &fixed_lds) && fixed_lds <= lds_limit()) {
         b->fixed = 1;
         b->pitch = b->arr = 0;
         return true;

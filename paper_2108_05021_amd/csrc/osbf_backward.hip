@@ -210,8 +210,9 @@ template <int R, int RW, int RH, int NT>
 __global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
     extern __shared__ float lds[];
     constexpr int PITCH = RW + 1, ARR = RH * PITCH, NY = NT / RW;
-    constexpr int MB = ((RH - 1) / R + NY - 1) / NY;  // column blocks per wave, at most
-    static_assert(RW == 64 && NT % 64 == 0, "one wave per region row");
+    // blocks of R rows per wave, at most: the q region spans at most RH - 2R rows
+    constexpr int MB = ((RH - 2 * R + R - 1) / R + NY - 1) / NY;
+    static_assert((RW == 64 || RW == 128) && NT % RW == 0, "whole waves per region row");
     float *const HL = lds;
     float *const HR = lds + ARR;
     float *const VF = lds + 2 * ARR;  // VF, then Gpad
@@ -376,36 +377,39 @@ __global__ __launch_bounds__(NT) void adjoint_fixed_kernel(BwdLaunch a) {
     }
 }
 
-// Region of the fixed adjoint kernel for radius r (width 64, 512 threads),
-// or 0 when the generic kernel serves r.
-static int adjoint_fixed_rows(int r) {
-    switch (r) {
-        case 1: case 2: case 3: case 4: return 48;
-        case 5: case 8: return 64;
-        default: return 0;
-    }
+// Regions (width x height, 512 threads) of the fixed adjoint kernel; other
+// radii take the generic kernel.
+struct AdjGeom { int r, rw, rh; };
+constexpr AdjGeom kAdjGeoms[] = {{1, 64, 48}, {2, 64, 48}, {3, 64, 48}, {4, 64, 48},
+                                 {5, 64, 64}, {8, 64, 64}, {10, 128, 64}, {16, 128, 96}};
+
+static const AdjGeom *adjoint_geom(int r) {
+    for (const auto &g : kAdjGeoms)
+        if (g.r == r) return &g;
+    return nullptr;
 }
 
-size_t adjoint_fixed_lds_bytes(int rh) { return (size_t)3 * rh * 65 * sizeof(float); }
+static size_t adjoint_fixed_lds_bytes(int rw, int rh) { return (size_t)3 * rh * (rw + 1) * sizeof(float); }
 
-bool adjoint_fixed_tile(int r, int *tw, int *th) {
-    const int rh = adjoint_fixed_rows(r);
-    if (!rh) return false;
-    *tw = ((64 - 4 * r) / r) * r;
-    *th = ((rh - 4 * r) / r) * r;
+bool adjoint_fixed_tile(int r, int *tw, int *th, size_t *lds_bytes) {
+    const AdjGeom *g = adjoint_geom(r);
+    if (!g) return false;
+    *tw = ((g->rw - 4 * r) / r) * r;
+    *th = ((g->rh - 4 * r) / r) * r;
+    *lds_bytes = adjoint_fixed_lds_bytes(g->rw, g->rh);
     return true;
 }
 
-template <int R, int RH>
+template <int R, int RW, int RH>
 static hipError_t launch_adjoint_fixed(const BwdLaunch &a, hipStream_t stream) {
-    const size_t lds = adjoint_fixed_lds_bytes(RH);
-    const void *fn = (const void *)adjoint_fixed_kernel<R, 64, RH, 512>;
+    const size_t lds = adjoint_fixed_lds_bytes(RW, RH);
+    const void *fn = (const void *)adjoint_fixed_kernel<R, RW, RH, 512>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const int blocks = a.tiles_x * a.tiles_y * a.planes;
-    hipLaunchKernelGGL((adjoint_fixed_kernel<R, 64, RH, 512>), dim3(blocks), dim3(512), lds, stream, a);
+    hipLaunchKernelGGL((adjoint_fixed_kernel<R, RW, RH, 512>), dim3(blocks), dim3(512), lds, stream, a);
     return hipGetLastError();
 }
 
@@ -419,12 +423,14 @@ void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr) {
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t stream) {
     if (a.fixed) {
         switch (a.r) {
-            case 1: return launch_adjoint_fixed<1, 48>(a, stream);
-            case 2: return launch_adjoint_fixed<2, 48>(a, stream);
-            case 3: return launch_adjoint_fixed<3, 48>(a, stream);
-            case 4: return launch_adjoint_fixed<4, 48>(a, stream);
-            case 5: return launch_adjoint_fixed<5, 64>(a, stream);
-            case 8: return launch_adjoint_fixed<8, 64>(a, stream);
+            case 1: return launch_adjoint_fixed<1, 64, 48>(a, stream);
+            case 2: return launch_adjoint_fixed<2, 64, 48>(a, stream);
+            case 3: return launch_adjoint_fixed<3, 64, 48>(a, stream);
+            case 4: return launch_adjoint_fixed<4, 64, 48>(a, stream);
+            case 5: return launch_adjoint_fixed<5, 64, 64>(a, stream);
+            case 8: return launch_adjoint_fixed<8, 64, 64>(a, stream);
+            case 10: return launch_adjoint_fixed<10, 128, 64>(a, stream);
+            case 16: return launch_adjoint_fixed<16, 128, 96>(a, stream);
             default: return hipErrorInvalidValue;
         }
     }

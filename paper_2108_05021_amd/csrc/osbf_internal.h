@@ -45,9 +45,9 @@ struct BwdLaunch {
 };
 
 void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr);
-// Tile of the fixed-geometry adjoint kernel for radius r (false if r is
-// served by the generic kernel).
-bool adjoint_fixed_tile(int r, int *tw, int *th);
+// Tile and LDS bytes of the fixed-geometry adjoint kernel for radius r
+// (false if r is served by the generic kernel).
+bool adjoint_fixed_tile(int r, int *tw, int *th, size_t *lds_bytes);
 
 // Batched rounds (64x48 fixed geometry, 512 threads).
 size_t batched_lds_bytes();

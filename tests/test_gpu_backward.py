@@ -38,7 +38,7 @@ def test_single_adjoint_sweep(dev, shape, r):
     np.testing.assert_allclose(gx.reshape(want.shape), want, rtol=0, atol=_tol(want))
 
 
-@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8, 10, 16])
 @pytest.mark.parametrize("shape", [(2, 150, 197), (1, 1, 1), (1, 5, 300), (1, 300, 5), (1, 97, 64)])
 def test_fixed_adjoint_matches_generic(dev, monkeypatch, shape, r):
     """The fixed-geometry adjoint and the generic one perform the same FP32
