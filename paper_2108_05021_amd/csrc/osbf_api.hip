@@ -566,6 +566,12 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
         for (const auto &t : kBatchK)
             if (t[0] == m.radius) k = t[1];
         if (!k) return fail(OSBF_ERROR_UNSUPPORTED, "image %d: batched radius %d not in {1,2,3,4,5,8,10,16}", j, m.radius);
+        // a plan osbf_autotune measured for this image's class on the batch's
+        // geometry sets its fusion depth
+        Plan tuned;
+        if (tuned_plan(m.planes, m.height, m.width, m.radius, m.iterations, (int)dtype, &tuned) &&
+            tuned.geom == GEOM_64x48)
+            k = tuned.k;
         k = std::min(k, m.iterations);
         for (; k >= 1; --k) {
             b.plan = make_plan(GEOM_64x48, kGeomDims[GEOM_64x48][0], kGeomDims[GEOM_64x48][1], m.radius, k);

@@ -51,3 +51,19 @@ def test_autotune_identity_cases(dev):
     x = torch.rand(1, 20, 30, device=dev)
     assert osbf.autotune(x, 0, 5) == {"tile": (0, 0), "fused": 0}
     assert osbf.autotune(x, 2, 0) == {"tile": (0, 0), "fused": 0}
+
+
+def test_batched_after_autotune_equals_single(dev):
+    """Batched images take the fusion depth of a tuned plan on their class
+    when it uses the batch's region; the results stay the per-image ones."""
+    rng = np.random.default_rng(9)
+    xs = [torch.from_numpy(synth.voronoi(h, w, 8, 0.05, rng, C=c)).to(dev)
+          for h, w, c in ((300, 420, 1), (1100, 1000, 1), (64, 900, 3))]
+    rs, ts = [2, 3, 1], [7, 5, 9]
+    osbf.autotune_clear()
+    for x, r, t in zip(xs, rs, ts):
+        osbf.autotune(x, r, t)
+    ys = osbf.batched(xs, rs, ts)
+    for x, y, r, t in zip(xs, ys, rs, ts):
+        assert torch.equal(y, osbf.forward(x, r, t))
+    osbf.autotune_clear()
