@@ -14,8 +14,13 @@
 // last 2r+1 slices.  Once the ring spans [z-r, z+r] the thread sums it along
 // z, selects among the 14 windows (scaled distances, tie order +x, -x, +y, -y,
 // +z, -z, then octants with x fastest and + first) and writes voxel z.
-// The next slice's global loads are issued before the current slice's LDS
-// work; the planar region is double-buffered, so three barriers per slice.
+// The vertical planar pass is fused with the slice load: each lane keeps the
+// rows its wave's column blocks need in registers (loaded one slice ahead),
+// forms V there and writes its P and V rows to LDS.  P and V are
+// double-buffered, so a slice costs two barriers; each voxel's store is
+// issued one slice late, ahead of the next slice's loads (loads and stores
+// share one memory counter, so the wait for those loads then does not wait
+// on fresh stores).
 #include <type_traits>
 
 #include "osbf_device.h"
@@ -109,11 +114,11 @@ __device__ __forceinline__ void planar_quantities(const float *P, const float *V
 template <int R, int NT, bool SEL>
 __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
     constexpr int RW = 64, PITCH = RW + 1, NY = NT / RW, TH = NY, RH = TH + 2 * R;
-    constexpr int ARR = RH * PITCH, NL = (RH + NY - 1) / NY, RING = 2 * R + 1;
+    constexpr int ARR = RH * PITCH, RING = 2 * R + 1;
+    constexpr int MB = ((TH + R + R - 1) / R + NY - 1) / NY;  // column blocks per wave, at most
     extern __shared__ float lds[];
-    float *const V = lds + 2 * ARR;
-    float *const Q = lds + 3 * ARR;
-    float *const Hs = lds + 4 * ARR;
+    float *const Q = lds + 4 * ARR;
+    float *const Hs = lds + 5 * ARR;
     const int tid = threadIdx.x, lx = tid % RW;
     const int ly = __builtin_amdgcn_readfirstlane(tid / RW);
     const int D = a.D, H = a.H, W = a.W, TW = a.tw;
@@ -135,25 +140,55 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
     float *dst = a.dst + (size_t)vol * D * slice;
     uint8_t *sel = SEL ? a.sel + (size_t)vol * D * slice : nullptr;
 
-    // this thread's (x, y) column and its loads of the planar region
+    // this thread's (x, y) column; its vertical blocks of R rows (V on rows
+    // [ya, yb+R), columns [max(0,xa-R), min(W,xb+R))) and their 2R input rows
     const int x = ox + lx, y = Y0 + ly;
     const bool own = x >= xa && x < xb && y < yb;
-    const bool ldx = x >= 0 && x < W && lx < TW + 2 * R;
-    const int ly0 = max(0, oy), ly1 = min(H, Y0 + TH + R);
-    float raw[NL];
-    auto load_slice = [&](int zs) {
-        const float *s = src + (size_t)min(max(zs, 0), D - 1) * slice;
-        if (ldx) {
+    const bool vx = x >= max(0, xa - R) && x < min(W, xb + R);
+    const int yend = yb + R;
+    const int nblk = (yend - ya + R - 1) / R;
+    float raw[MB][2 * R];
+    auto load_rows = [&](int zs) {
+        const float *sl_ = src + (size_t)min(max(zs, 0), D - 1) * slice;
+        if (vx) {
 #pragma unroll
-            for (int i = 0; i < NL; ++i) raw[i] = s[(size_t)min(ly0 + ly + i * NY, ly1 - 1) * W + x];
+            for (int i = 0; i < MB; ++i) {
+                const int b = ly + i * NY;
+                if (b < nblk) {
+                    const int y0 = ya + b * R;
+#pragma unroll
+                    for (int tt = 0; tt < 2 * R; ++tt)
+                        raw[i][tt] = sl_[(size_t)min(max(y0 - R + tt, 0), H - 1) * W + x];
+                }
+            }
         }
     };
-    auto store_slice = [&](float *P) {
-        if (ldx) {
+    // V and the blocks' own P rows from the registers (the FP32 operations of
+    // fixed_phase_v)
+    auto v_phase = [&](float *P, float *V) {
+        if (!vx) return;
 #pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const int yy = ly0 + ly + i * NY;
-                if (yy < ly1) P[(yy - oy) * PITCH + lx] = raw[i];
+        for (int i = 0; i < MB; ++i) {
+            const int b = ly + i * NY;
+            if (b >= nblk) break;
+            const int y0 = ya + b * R;
+            const float *p = raw[i];
+#pragma unroll
+            for (int tt = 0; tt < R; ++tt) {
+                const int yy = y0 + tt;
+                if (yy < yend && yy < H) P[(yy - oy) * PITCH + lx] = p[R + tt];
+            }
+            float *vc = V + (y0 - oy) * PITCH + lx;
+            float v = p[0];
+#pragma unroll
+            for (int tt = 1; tt <= R; ++tt) v += p[tt];
+            vc[0] = v;
+#pragma unroll
+            for (int tt = 1; tt < R; ++tt) {
+                if (y0 + tt < yend) {
+                    v += p[R + tt] - p[tt - 1];
+                    vc[tt * PITCH] = v;
+                }
             }
         }
     };
@@ -163,20 +198,27 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
     const float invN = 1.0f / N;
     float ring[RING][NQ], cring[RING];
 
-    load_slice(z0 - R);
+    // deferred store of the previous voxel (value, map index, position)
+    float out_v = 0.f;
+    int out_i = 0;
+    size_t out_at = 0;
+    bool out_pending = false;
+
+    load_rows(z0 - R);
     for (int base = 0; base < nsl; base += RING) {
         static_for<0, RING>([&](auto S) {
             constexpr int s = decltype(S)::value;
             const int n = base + s;
             if (n >= nsl) return;  // uniform over the workgroup
             float *P = lds + (n & 1) * ARR;
-            store_slice(P);
-            if (n + 1 < nsl) load_slice(z0 - R + n + 1);
-            __syncthreads();
-            if (interior)
-                fixed_phase_v<R, RW, RH, NT, false>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
-            else
-                fixed_phase_v<R, RW, RH, NT, true>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
+            float *V = lds + (2 + (n & 1)) * ARR;
+            v_phase(P, V);
+            if (out_pending) {
+                dst[out_at] = out_v;
+                if (SEL) sel[out_at] = (uint8_t)out_i;
+                out_pending = false;
+            }
+            if (n + 1 < nsl) load_rows(z0 - R + n + 1);
             __syncthreads();
             if (interior)
                 phase_qh_items<R, RW, NT, false>(P, V, Q, Hs, tid, ox, oy, W, xa, xb, ya, yb);
@@ -228,10 +270,15 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
             duel(e4, i4, e6, i6);
             duel(e0, i0, e4, i4);
             const int z = z0 + n - 2 * R;
-            const size_t gi = (size_t)z * slice + (size_t)y * W + x;
-            dst[gi] = fmaf(e0, invN, c);
-            if (SEL) sel[gi] = (uint8_t)i0;
+            out_at = (size_t)z * slice + (size_t)y * W + x;
+            out_v = fmaf(e0, invN, c);
+            out_i = i0;
+            out_pending = true;
         });
+    }
+    if (out_pending) {
+        dst[out_at] = out_v;
+        if (SEL) sel[out_at] = (uint8_t)out_i;
     }
 }
 
@@ -242,7 +289,7 @@ void fwd3d_geometry(int r, int *tw, int *th) {
     *th = 512 / 64;
 }
 
-size_t fwd3d_lds_bytes(int r) { return (size_t)5 * (512 / 64 + 2 * r) * 65 * sizeof(float); }
+size_t fwd3d_lds_bytes(int r) { return (size_t)6 * (512 / 64 + 2 * r) * 65 * sizeof(float); }
 
 template <int R>
 static hipError_t launch3d(const Fwd3dLaunch &a, hipStream_t stream) {
