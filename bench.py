@@ -50,9 +50,12 @@ H = W = 2048
 C = 3
 
 
-# sources that define the planar forward kernel (its launch shape is checked
-# separately through the plans)
-FWD_KERNEL_SOURCES = ("osbf_device.h", "osbf_fwd_device.h", "osbf_forward.hip")
+# sources that define the planar forward kernels (their launch shape is
+# checked separately through the plans)
+FWD_KERNEL_SOURCES = ("osbf_device.h", "osbf_fwd_device.h", "osbf_forward.hip", "osbf_stream_device.h",
+                      "osbf_stream.hip")
+# the kernel the bench plans launch for r in RADII (the row-streaming kernel)
+FWD_KERNEL_NAME = "osbf::fwd_stream_kernel"
 
 
 def kernel_source_hash() -> str:
@@ -405,7 +408,7 @@ def main():
                    "planes": C, "height": H, "width": W, "radii": list(RADII), "iterations": T_SWEEPS},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "osbf::fwd_fixed_kernel", "kernels": kernels,
+                     "kernel": FWD_KERNEL_NAME, "kernels": kernels,
                      "bytes_per_px_sweep": BYTES_PER_PX_SWEEP},
     }
     if not args.no_cpu_baseline:

@@ -218,10 +218,12 @@ osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype,
 
 /*
  * osbf_forward_plan -- the launch plan osbf_forward uses for these arguments
- * (for profiling and tests; no device work).  Writes the output tile shape,
- * the sweeps fused per launch and the number of kernel launches (per chunk
- * of at most 65535 planes); ck as for osbf_forward (0 = no checkpoints).
- * Returns OSBF_ERROR_UNSUPPORTED when no tiled plan fits the device's LDS.
+ * (for profiling and tests; no device work).  Writes the output tile shape
+ * (tiled kernels: tile width x height; row-streaming kernel: strip width x
+ * rows per workgroup), the sweeps fused per launch (always 1 for the
+ * streaming kernel) and the number of kernel launches (per chunk of at most
+ * 65535 planes); ck as for osbf_forward (0 = no checkpoints).  Returns
+ * OSBF_ERROR_UNSUPPORTED when no plan fits the device's LDS.
  */
 osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osbf_dtype dtype,
                               int32_t radius, int32_t iterations, int32_t ck,
@@ -233,16 +235,19 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osb
  * and keep the fastest for the calling thread's device.
  *   src, dst   distinct device buffers of [planes][height][width] elements of
  *              dtype; src is read, dst is overwritten (scratch)
- * Times every fixed LDS geometry and fusion depth that fits (and the cost
- * model's generic plan) with HIP events, a few launches each, on `stream`,
+ * Times every fixed LDS geometry and fusion depth that fits, the
+ * row-streaming kernel's strip widths with a few row counts per workgroup,
+ * and the cost model's generic plan, with HIP events, a few launches each,
+ * on `stream`,
  * and blocks until done (do not call during stream capture).  The winner is
  * cached per (device, radius, dtype, size class: planes*height*width below or
  * at least 2^20) and used by later osbf_forward / osbf_backward /
  * osbf_forward_plan calls of that class, and by batched images of that class
  * when the tuned plan uses the batch's 64x48 region (its fusion depth);
  * OSBF_PLAN in the environment still takes precedence for single images.
- * Batched workspace sizes depend on the cache: tune before sizing a batch.  Every plan computes the same bits, so tuning changes
- * speed, never results.  Writes the chosen tile and fused sweeps (0 for
+ * Batched workspace sizes depend on the cache: tune before sizing a batch.
+ * Every plan computes the same bits, so tuning changes speed, never
+ * results.  Writes the chosen tile and fused sweeps (0 for
  * radius 0 or iterations 0).  The cache is process state guarded by a mutex.
  */
 osbf_status osbf_autotune(const void *src, void *dst, int32_t planes, int32_t height, int32_t width,

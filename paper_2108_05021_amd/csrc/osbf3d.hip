@@ -21,21 +21,11 @@
 // issued one slice late, ahead of the next slice's loads (loads and stores
 // share one memory counter, so the wait for those loads then does not wait
 // on fresh stores).
-#include <type_traits>
-
 #include "osbf_device.h"
 #include "osbf_fwd_device.h"
 #include "osbf_internal.h"
 
 namespace osbf {
-
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(f);
-    }
-}
 
 // Q on columns [xa, xb+R), rows [ya, yb+R) and H on the same columns, rows
 // [ya, yb), like fixed_phase_qh, but with (row, block of R columns) work items

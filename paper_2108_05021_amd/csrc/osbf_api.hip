@@ -63,7 +63,8 @@ struct Plan {
     int tw = 0, th = 0;  // output tile (multiples of r); tw == 0: nothing fits
     int k = 1;           // sweeps fused per launch
     int pitch = 0, arr = 0;
-    size_t lds_bytes() const { return (size_t)4 * arr * sizeof(float); }
+    size_t lds = 0;      // streaming kernel: its LDS bytes (th: rows per workgroup)
+    size_t lds_bytes() const { return lds ? lds : (size_t)4 * arr * sizeof(float); }
 };
 
 // LDS regions (width x height, halo included) the generic kernel considers.
@@ -72,6 +73,16 @@ const int kRegions[][2] = {{64, 64}, {128, 64}, {64, 128}, {96, 96}, {128, 128},
 
 Plan make_plan(int geom, int RW, int RH, int r, int k) {
     Plan p;
+    if (stream_geom(geom)) {  // one sweep per launch; strips of whole blocks of r columns
+        const int tw = ((RW - 2 * r) / r) * r;
+        if (k != 1 || !fixed_radius(r) || tw < std::max(r, 4)) return Plan{};
+        p.geom = geom;
+        p.tw = tw;
+        p.th = stream_default_rows(r, RW);
+        p.k = 1;
+        p.lds = stream_lds_bytes(RW, r);
+        return p;
+    }
     if (!fwd_tile_shape(RW, RH, r, k, &p.tw, &p.th)) return Plan{};
     p.geom = geom;
     p.k = k;
@@ -88,6 +99,8 @@ Plan make_plan(int geom, int RW, int RH, int r, int k) {
 // regions (halo recomputation), the cheaper running-sum phases and the halo
 // load, HBM traffic that shrinks as 1/k, and a penalty for low occupancy.
 double plan_cost(const Plan &p, int H, int W, int r) {
+    if (stream_geom(p.geom))  // selection on tw of RW columns, no vertical halo to speak of
+        return 0.75 * kGeomDims[p.geom][0] / std::min(p.tw, W) + 0.25;
     const double tw = std::min(p.tw, W), th = std::min(p.th, H);
     double work = 0;
     for (int j = 0; j < p.k; ++j) {
@@ -109,13 +122,19 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 }
 
 // Measured defaults for the compiled radii (3x2048x2048 FP32, T=30 on
-// MI355X, plan sweep over geometries and fusion depths): 512-thread 64-wide
-// regions up to r=10, the 1024-thread 128x64 region for r=16; fusion pays
-// off for r <= 3.
+// MI355X, plan sweep over geometries, fusion depths and streaming rows), in
+// order of preference: the row-streaming kernel from r=2 up, the tiled
+// kernel with three fused sweeps at r=1 (the later entries are fallbacks
+// for devices whose LDS does not fit the first).
 struct TunedShape { int r, geom, k; };
-const TunedShape kTuned[] = {{1, GEOM_64x48, 3}, {2, GEOM_64x48, 2}, {3, GEOM_64x48, 2},
-                             {4, GEOM_64x48, 1}, {5, GEOM_64x60, 1}, {8, GEOM_64x48, 1},
-                             {10, GEOM_64x60, 1}, {16, GEOM_128x64, 1}};
+const TunedShape kTuned[] = {{1, GEOM_64x48, 3},
+                             {2, GEOM_S128, 1}, {2, GEOM_64x48, 2},
+                             {3, GEOM_S256, 1}, {3, GEOM_64x48, 2},
+                             {4, GEOM_S256, 1}, {4, GEOM_64x48, 1},
+                             {5, GEOM_S256, 1}, {5, GEOM_64x60, 1},
+                             {8, GEOM_S256, 1}, {8, GEOM_64x48, 1},
+                             {10, GEOM_S128, 1}, {10, GEOM_64x60, 1},
+                             {16, GEOM_S128, 1}, {16, GEOM_128x64, 1}};
 
 // Autotune cache: (device, radius, dtype, size class) -> plan measured by
 // osbf_autotune.  Guarded by a mutex; every plan gives the same bits, so the
@@ -124,6 +143,13 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, Plan> g_tune;
 
 int size_class(int planes, int H, int W) { return (long long)planes * H * W >= (1LL << 20) ? 1 : 0; }
+
+// Rows per workgroup of a plan (the streaming kernel rounds to whole steps).
+int plan_rows(const Plan &p, int r) {
+    if (!stream_geom(p.geom)) return p.th;
+    const int step = stream_step(r);
+    return (std::max(p.th, 1) + step - 1) / step * step;
+}
 
 bool tuned_plan(int planes, int H, int W, int r, int T, int dtype, Plan *out) {
     int dev = 0;
@@ -147,15 +173,17 @@ Plan choose_plan(int planes, int H, int W, int r, int T, int dtype) {
     return choose_plan_model(H, W, r, T);
 }
 
-// OSBF_PLAN="geom,k" forces a plan (tests and tuning): geom 0 is the generic
-// kernel (region chosen by cost), 1.. the fixed geometries (enum Geom).
+// OSBF_PLAN="geom,k[,rows]" forces a plan (tests and tuning): geom 0 is the
+// generic kernel (region chosen by cost), 1.. the fixed and streaming
+// geometries (enum Geom); rows sets the streaming kernel's rows per workgroup.
 Plan choose_plan_model(int H, int W, int r, int T) {
     const size_t limit = lds_limit();
     const int kmax = T > 0 ? std::min(T, 8) : 1;
-    int force_geom = -1, force_k = -1;
+    int force_geom = -1, force_k = -1, force_rows = 0;
     if (const char *env = getenv("OSBF_PLAN")) {
-        if (sscanf(env, "%d,%d", &force_geom, &force_k) != 2 || force_geom < 0 || force_geom >= NUM_GEOMS || force_k < 1)
-            force_geom = force_k = -1;
+        const int n = sscanf(env, "%d,%d,%d", &force_geom, &force_k, &force_rows);
+        if (n < 2 || force_geom < 0 || force_geom >= NUM_GEOMS || force_k < 1 || force_rows < 0)
+            force_geom = force_k = -1, force_rows = 0;
         else
             force_k = std::min(force_k, kmax);
     }
@@ -182,6 +210,7 @@ Plan choose_plan_model(int H, int W, int r, int T) {
         if (force_geom <= 0)
             for (const auto &reg : kRegions) consider(make_plan(GEOM_GENERIC, reg[0], reg[1], r, k));
     }
+    if (best.tw && stream_geom(best.geom) && force_rows > 0) best.th = force_rows;
     if (!best.tw && force_geom >= 0) {   // forced plan does not fit: fall back to the model
         for (int k = 1; k <= kmax; ++k) {
             if (fixed_radius(r))
@@ -215,7 +244,8 @@ hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, u
                            int planes, int H, int W, int r, osbf_dtype dtype, hipStream_t stream,
                            int mode = 0) {
     const size_t plane_set = (size_t)planes * H * W;
-    const int tiles_x = (W + plan.tw - 1) / plan.tw, tiles_y = (H + plan.th - 1) / plan.th;
+    const int th = plan_rows(plan, r);
+    const int tiles_x = (W + plan.tw - 1) / plan.tw, tiles_y = (H + th - 1) / th;
     const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)tiles_x * tiles_y)));
     for (int p0 = 0; p0 < planes; p0 += max_planes) {
         const int np = std::min(max_planes, planes - p0);
@@ -227,7 +257,7 @@ hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, u
         a.sel_stride = (long long)plane_set;
         a.planes = np;
         a.H = H; a.W = W; a.r = r; a.k = k;
-        a.tw = plan.tw; a.th = plan.th;
+        a.tw = plan.tw; a.th = th;
         a.tiles_x = tiles_x; a.tiles_y = tiles_y;
         a.geom = plan.geom;
         if (plan.geom == GEOM_GENERIC)
@@ -516,7 +546,7 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t H, int32_t W, osbf_dtype d
     if (!plan.tw)
         return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
     *tile_w = plan.tw;
-    *tile_h = plan.th;
+    *tile_h = plan_rows(plan, r);
     *fused = plan.k;
     *launches = (int32_t)make_launches(T, ck > 0 ? ck : 0, plan.k).size();
     return OSBF_SUCCESS;
@@ -903,7 +933,14 @@ osbf_status osbf_autotune(const void *src, void *dst, int32_t planes, int32_t H,
         for (int g = 1; g < NUM_GEOMS; ++g)
             for (int k = 1; k <= kmax; ++k) {
                 const Plan p = make_plan(g, kGeomDims[g][0], kGeomDims[g][1], r, k);
-                if (p.tw && p.lds_bytes() <= limit) cands.push_back(p);
+                if (!p.tw || p.lds_bytes() > limit) continue;
+                cands.push_back(p);
+                if (stream_geom(g))  // and other rows per workgroup
+                    for (int rows : {16, 32, 64, 96}) {
+                        Plan q = p;
+                        q.th = rows;
+                        if (plan_rows(q, r) != plan_rows(p, r)) cands.push_back(q);
+                    }
             }
     {
         Plan best;
@@ -955,7 +992,7 @@ osbf_status osbf_autotune(const void *src, void *dst, int32_t planes, int32_t H,
         g_tune[std::make_tuple(dev, r, (int)dtype, size_class(planes, H, W))] = best;
     }
     *tile_w = best.tw;
-    *tile_h = best.th;
+    *tile_h = plan_rows(best, r);
     *fused = best.k;
     return OSBF_SUCCESS;
 }

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace osbf {
 
 // Storage types of the iterate.  Arithmetic is always FP32; the iterate is
@@ -87,6 +89,16 @@ __device__ __forceinline__ Pick select8(const float d[8]) {
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// f(integral_constant<int, I>) for I = I0 .. N-1, unrolled at compile time
+// (register arrays indexed by I stay in registers).
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
 
 // XCD-aware tile order: the 8 XCDs take workgroups round-robin, so linear
 // workgroup b runs on XCD b % 8.  Give each XCD a contiguous run of tiles so

@@ -60,6 +60,7 @@ static hipError_t launch_mode_r(const FwdLaunch &a, hipStream_t s) {
 }
 
 hipError_t launch_forward_mode(int mode, int dtype, const FwdLaunch &a, hipStream_t s) {
+    if (stream_geom(a.geom)) return launch_forward_stream_mode(mode, dtype, a, s);
     if (mode == MODE_FAST) {
         switch (dtype) {
         case DT_F32: return launch_mode_r<DT_F32, MODE_FAST>(a, s);

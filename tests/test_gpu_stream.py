@@ -1,0 +1,105 @@
+"""GPU parity of the row-streaming forward kernel (geometries 5 and 6: strips
+of 128 or 256 lanes walking down chunks of rows, one sweep per launch; the
+exact filter, the fast approximation and the box filter).
+
+Its running sums restart at the same image positions as in the tiled kernels
+and add in the same order, so on every shape, radius, storage type and chunk
+height its output and selection maps must equal the tiled kernel's bit for
+bit; the first sweep is also checked against the FP64 oracle."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2108_05021_amd import osbf, synth
+from tests.parity import check_sweep_planes
+
+pytestmark = pytest.mark.gpu
+
+STEP = {1: 2, 2: 4, 3: 3, 4: 4, 5: 5, 8: 8, 10: 10, 16: 16}
+
+
+class plan:
+    def __init__(self, *v):
+        self.v = ",".join(str(a) for a in v)
+
+    def __enter__(self):
+        self.old = os.environ.get("OSBF_PLAN")
+        os.environ["OSBF_PLAN"] = self.v
+
+    def __exit__(self, *a):
+        if self.old is None:
+            os.environ.pop("OSBF_PLAN", None)
+        else:
+            os.environ["OSBF_PLAN"] = self.old
+
+
+def _plan_shape(planes, H, W, r, T=1):
+    p = osbf.forward_plan(planes, H, W, torch.float32, r, T)
+    return p["tile"][0], p["tile"][1], p["fused"], p["launches"]
+
+
+@pytest.mark.parametrize("geom", [5, 6])
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8, 10, 16])
+def test_stream_equals_tiled(dev, geom, r):
+    rng = np.random.default_rng(700 + 10 * r + geom)
+    for shape in [(2, 97, 301), (1, 260, 70), (1, 3, 500), (1, 500, 3), (1, 1, 1)]:
+        img = synth.voronoi(shape[1], shape[2], 9, 0.05, rng, C=shape[0])
+        x = torch.from_numpy(img).to(dev)
+        with plan(1, 1):
+            want, wsel = osbf.forward(x, r, 2, return_sel=True)
+        for rows in (0, STEP[r], 3 * STEP[r] + 1):
+            with plan(geom, 1, rows):
+                tw, th, k, _ = _plan_shape(*shape, r)
+                assert k == 1 and tw % r == 0 and th % STEP[r] == 0 and th >= STEP[r]
+                y, sel = osbf.forward(x, r, 2, return_sel=True)
+                y2 = osbf.forward(x, r, 2)
+            assert torch.equal(y, want) and torch.equal(sel, wsel), (shape, rows)
+            assert torch.equal(y2, want), (shape, rows)
+        if shape[1] * shape[2] > 1000:
+            with plan(geom, 1):
+                y1, s1 = osbf.forward(x, r, 1, return_sel=True)
+            st = check_sweep_planes(img, y1.cpu().numpy(), r, s1[0].cpu().numpy())
+            assert st["flips"] <= max(2, st["pixels"] // 1000)
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("r", [2, 5, 16])
+def test_stream_reduced_precision_equals_tiled(dev, dtype, r):
+    rng = np.random.default_rng(800 + r)
+    img = synth.voronoi(210, 333, 11, 0.03, rng, C=2)
+    x = torch.from_numpy(img).to(dev).to(dtype)
+    with plan(1, 1):
+        want = osbf.forward(x, r, 3)
+        wsel = osbf.forward(x, r, 1, return_sel=True)[1]
+    with plan(5, 1):
+        y = osbf.forward(x, r, 3)
+        sel = osbf.forward(x, r, 1, return_sel=True)[1]
+    assert torch.equal(y, want) and torch.equal(sel, wsel)
+
+
+def test_stream_full_size_equals_tiled(dev):
+    """3x2048x2048 (the benchmark image), r=10, T=3: the streaming plan in its
+    automatic chunking equals the tiled plan bit for bit."""
+    x = torch.from_numpy(synth.workload_rgb()).to(dev)
+    with plan(3, 1):
+        want = osbf.forward(x, 10, 3)
+    for geom in (5, 6):
+        with plan(geom, 1):
+            assert torch.equal(osbf.forward(x, 10, 3), want)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 5, 10, 16])
+def test_stream_modes_equal_tiled(dev, r):
+    """The fast approximation (Alg. 3) and the classical box filter on the
+    streaming kernel give the tiled kernel's bits."""
+    rng = np.random.default_rng(900 + r)
+    x = torch.from_numpy(synth.voronoi(170, 290, 7, 0.05, rng, C=2)).to(dev)
+    with plan(1, 1):
+        f = osbf.forward_fast(x, r, 3)
+        b = osbf.box_forward(x, r, 3)
+    for geom in (5, 6):
+        with plan(geom, 1):
+            assert torch.equal(osbf.forward_fast(x, r, 3), f)
+            assert torch.equal(osbf.box_forward(x, r, 3), b)
