@@ -71,6 +71,24 @@ __global__ __launch_bounds__(RW) void fwd_stream_kernel(FwdLaunch a) {
     T *dst = (T *)a.dst + plane_off;
     uint8_t *sel = SEL ? a.sel + plane_off : nullptr;
 
+    // This lane's row-sum work items, the same in every step: items of one
+    // block of R rows are consecutive, row fastest, so 32 consecutive lanes
+    // read 32 distinct banks (row pitch = 1 mod 32, column blocks R apart)
+    // when R divides 32.  CH * nb <= M * RW, so a lane has at most M items.
+    const int nb = (xend - xa + R - 1) / R;
+    int it_row[M], it_x0[M];
+    bool it_ok[M], it_fast[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int it = lx + k * RW;
+        const int m = it / (R * nb), rem = it - m * (R * nb);
+        const int b = rem / R;
+        it_ok[k] = it < CH * nb;
+        it_row[k] = m * R + (rem - b * R);
+        it_x0[k] = xa + b * R;
+        it_fast[k] = it_x0[k] - R >= lo && it_x0[k] + R - 1 <= hi;  // no column clamped
+    }
+
     constexpr float fr1 = (float)(R + 1), f2r1 = (float)(2 * R + 1);
     constexpr float N = fr1 * fr1 * f2r1;
     const float invN = 1.0f / N;
@@ -139,21 +157,14 @@ __global__ __launch_bounds__(RW) void fwd_stream_kernel(FwdLaunch a) {
 
         // Q and H of rows [s, s + CH) ∩ [Y0, yend), columns [xa, xend), into
         // ring blocks base + 1 .. base + M
-        {
-            // items of one block of R rows are consecutive, row fastest: 32
-            // consecutive lanes then read 32 distinct banks (row pitch = 1
-            // mod 32, column blocks R apart) when R divides 32
-            const int nb = (xend - xa + R - 1) / R;
-            const int nitems = CH * nb;
-            for (int it = lx; it < nitems; it += RW) {
-                const int m = it / (R * nb), rem = it - m * (R * nb);
-                const int b = rem / R, i = m * R + (rem - b * R);
-                if (s + i >= yend) continue;
-                const int x0 = xa + b * R;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int i = it_row[k], x0 = it_x0[k];
+            if (it_ok[k] && s + i < yend) {
                 const float *vrow = Vl + i * PITCH - ox;  // + image column
                 const float *prow = Pl + i * PITCH - ox;
                 float v[2 * R], p[2 * R];
-                if (x0 - R >= lo && x0 + R - 1 <= hi) {  // no column clamped: immediate offsets
+                if (it_fast[k]) {  // immediate offsets
 #pragma unroll
                     for (int tt = 0; tt < 2 * R; ++tt) {
                         v[tt] = vrow[x0 - R + tt];
