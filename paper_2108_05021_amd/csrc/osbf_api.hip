@@ -78,7 +78,7 @@ Plan make_plan(int geom, int RW, int RH, int r, int k) {
         if (k != 1 || !fixed_radius(r) || tw < std::max(r, 4)) return Plan{};
         p.geom = geom;
         p.tw = tw;
-        p.th = stream_default_rows(r, RW);
+        p.th = 0;  // rows per workgroup chosen at launch to fill the device once
         p.k = 1;
         p.lds = stream_lds_bytes(RW, r);
         return p;
@@ -122,19 +122,21 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 }
 
 // Measured defaults for the compiled radii (3x2048x2048 FP32, T=30 on
-// MI355X, plan sweep over geometries, fusion depths and streaming rows), in
-// order of preference: the row-streaming kernel from r=2 up, the tiled
-// kernel with three fused sweeps at r=1 (the later entries are fallbacks
-// for devices whose LDS does not fit the first).
-struct TunedShape { int r, geom, k; };
-const TunedShape kTuned[] = {{1, GEOM_64x48, 3},
-                             {2, GEOM_S128, 1}, {2, GEOM_64x48, 2},
-                             {3, GEOM_S256, 1}, {3, GEOM_64x48, 2},
-                             {4, GEOM_S256, 1}, {4, GEOM_64x48, 1},
-                             {5, GEOM_S256, 1}, {5, GEOM_64x60, 1},
-                             {8, GEOM_S256, 1}, {8, GEOM_64x48, 1},
-                             {10, GEOM_S128, 1}, {10, GEOM_64x60, 1},
-                             {16, GEOM_S128, 1}, {16, GEOM_128x64, 1}};
+// MI355X, plan sweep over geometries, fusion depths, streaming strip widths
+// and rows per workgroup, 0 = chosen to fill the device once), in order of
+// preference: the
+// row-streaming kernel from r=2 up, the tiled kernel with three fused sweeps
+// at r=1 (the later entries are fallbacks for devices whose LDS does not fit
+// the first).
+struct TunedShape { int r, geom, k, rows; };
+const TunedShape kTuned[] = {{1, GEOM_64x48, 3, 0},
+                             {2, GEOM_S192, 1, 32}, {2, GEOM_64x48, 2, 0},
+                             {3, GEOM_S128, 1, 0}, {3, GEOM_64x48, 2, 0},
+                             {4, GEOM_S256, 1, 32}, {4, GEOM_64x48, 1, 0},
+                             {5, GEOM_S192, 1, 48}, {5, GEOM_64x60, 1, 0},
+                             {8, GEOM_S192, 1, 0}, {8, GEOM_64x48, 1, 0},
+                             {10, GEOM_S192, 1, 0}, {10, GEOM_64x60, 1, 0},
+                             {16, GEOM_S192, 1, 0}, {16, GEOM_128x64, 1, 0}};
 
 // Autotune cache: (device, radius, dtype, size class) -> plan measured by
 // osbf_autotune.  Guarded by a mutex; every plan gives the same bits, so the
@@ -144,11 +146,13 @@ std::map<std::tuple<int, int, int, int>, Plan> g_tune;
 
 int size_class(int planes, int H, int W) { return (long long)planes * H * W >= (1LL << 20) ? 1 : 0; }
 
-// Rows per workgroup of a plan (the streaming kernel rounds to whole steps).
+// Rows per workgroup of a plan (the streaming kernel rounds to whole steps;
+// 0: chosen at launch so that the chunks fill the device's resident
+// workgroup slots once).
 int plan_rows(const Plan &p, int r) {
-    if (!stream_geom(p.geom)) return p.th;
+    if (!stream_geom(p.geom) || p.th <= 0) return p.th;
     const int step = stream_step(r);
-    return (std::max(p.th, 1) + step - 1) / step * step;
+    return (p.th + step - 1) / step * step;
 }
 
 bool tuned_plan(int planes, int H, int W, int r, int T, int dtype, Plan *out) {
@@ -191,6 +195,7 @@ Plan choose_plan_model(int H, int W, int r, int T) {
         for (const auto &t : kTuned) {
             if (t.r != r) continue;
             Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
+            if (stream_geom(t.geom)) p.th = t.rows;
             if (p.tw && p.lds_bytes() <= limit) return p;
         }
     }
@@ -245,7 +250,7 @@ hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, u
                            int mode = 0) {
     const size_t plane_set = (size_t)planes * H * W;
     const int th = plan_rows(plan, r);
-    const int tiles_x = (W + plan.tw - 1) / plan.tw, tiles_y = (H + th - 1) / th;
+    const int tiles_x = (W + plan.tw - 1) / plan.tw, tiles_y = th > 0 ? (H + th - 1) / th : 1;
     const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)tiles_x * tiles_y)));
     for (int p0 = 0; p0 < planes; p0 += max_planes) {
         const int np = std::min(max_planes, planes - p0);

@@ -66,7 +66,7 @@ static hipError_t launch_fwd_r(const FwdLaunch &a, hipStream_t s) {
     }
 }
 
-const int kGeomDims[NUM_GEOMS][2] = {{0, 0}, {64, 48}, {64, 32}, {64, 60}, {128, 64}, {128, 0}, {256, 0}};
+const int kGeomDims[NUM_GEOMS][2] = {{0, 0}, {64, 48}, {64, 32}, {64, 60}, {128, 64}, {128, 0}, {256, 0}, {192, 0}};
 
 bool fixed_radius(int r) {
     return r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 8 || r == 10 || r == 16;

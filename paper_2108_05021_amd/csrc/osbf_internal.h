@@ -24,18 +24,19 @@ struct FwdLaunch {
 // kernel (one sweep per launch) whose workgroup walks down a strip of the
 // given width.
 enum Geom : int { GEOM_GENERIC = 0, GEOM_64x48 = 1, GEOM_64x32 = 2, GEOM_64x60 = 3, GEOM_128x64 = 4,
-                  GEOM_S128 = 5, GEOM_S256 = 6, NUM_GEOMS = 7 };
+                  GEOM_S128 = 5, GEOM_S256 = 6, GEOM_S192 = 7, NUM_GEOMS = 8 };
 extern const int kGeomDims[NUM_GEOMS][2];   // region width, height (0 for generic and streaming)
 bool fixed_radius(int r);
-inline bool stream_geom(int g) { return g == GEOM_S128 || g == GEOM_S256; }
+inline bool stream_geom(int g) { return g == GEOM_S128 || g == GEOM_S256 || g == GEOM_S192; }
 
 // Output tile for an LDS region of at most RW x RH pixels (false if none).
 bool fwd_tile_shape(int RW, int RH, int r, int k, int *tw, int *th);
 void fwd_lds_layout(int tw, int th, int r, int k, int *pitch, int *arr);
 hipError_t launch_forward(int dtype, const FwdLaunch &a, hipStream_t s);
-// Row-streaming kernel (k = 1, any mode): strips of tw columns, chunks of th rows.
+// Row-streaming kernel (k = 1, any mode): strips of tw columns, chunks of th
+// rows (th = 0: the launch chooses th so that the chunks fill the device's
+// resident workgroup slots once).
 int stream_step(int r);                       // rows per step (th is a multiple)
-int stream_default_rows(int r, int RW);       // rows per workgroup, a multiple of the step
 size_t stream_lds_bytes(int RW, int r);
 hipError_t launch_forward_stream(int dtype, const FwdLaunch &a, hipStream_t s);
 hipError_t launch_forward_stream_mode(int mode, int dtype, const FwdLaunch &a, hipStream_t s);

@@ -20,6 +20,9 @@
 // running sum restarts at the same image coordinates as in the tiled kernels
 // and sums in the same order, so results and maps are bit-identical to them.
 #pragma once
+#include <algorithm>
+#include <atomic>
+
 #include "osbf_device.h"
 #include "osbf_fwd_device.h"
 #include "osbf_internal.h"
@@ -273,24 +276,57 @@ hipError_t launch_stream(const FwdLaunch &a, hipStream_t stream) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    const int blocks = a.tiles_x * a.tiles_y * a.planes;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(RW), lds, stream, a);
+    FwdLaunch b = a;
+    if (a.th <= 0) {
+        // rows per workgroup chosen so that the strips' chunks fill the
+        // device's resident workgroup slots once (no partial last wave)
+        static std::atomic<int> slots[64];  // per device; 0 = not yet queried
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        int n = dev < 64 ? slots[dev].load(std::memory_order_relaxed) : 0;
+        if (!n) {
+            int cus = 0, per_cu = 0;
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, RW, lds);
+            if (e != hipSuccess) return e;
+            n = std::max(1, cus * per_cu);
+            if (dev < 64) slots[dev].store(n, std::memory_order_relaxed);
+        }
+        const long long strips = (long long)a.tiles_x * a.planes;
+        const int per_strip = (int)std::max<long long>(1, n / strips);
+        int rows = (a.H + per_strip - 1) / per_strip;
+        rows = std::max(CH, (rows + CH - 1) / CH * CH);
+        b.th = rows;
+        b.tiles_y = (a.H + rows - 1) / rows;
+    }
+    const int blocks = b.tiles_x * b.tiles_y * b.planes;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(RW), lds, stream, b);
     return hipGetLastError();
+}
+
+template <int DT, int R, bool SEL, int MODE>
+hipError_t launch_stream_w(const FwdLaunch &a, hipStream_t s) {
+    switch (a.geom) {
+    case GEOM_S128: return launch_stream<DT, R, 128, SEL, MODE>(a, s);
+    case GEOM_S192: return launch_stream<DT, R, 192, SEL, MODE>(a, s);
+    case GEOM_S256: return launch_stream<DT, R, 256, SEL, MODE>(a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int DT, bool SEL, int MODE>
 hipError_t launch_stream_r(const FwdLaunch &a, hipStream_t s) {
     if (a.k != 1 || !stream_geom(a.geom)) return hipErrorInvalidValue;
-    const bool w = a.geom == GEOM_S256;
     switch (a.r) {
-    case 1: return w ? launch_stream<DT, 1, 256, SEL, MODE>(a, s) : launch_stream<DT, 1, 128, SEL, MODE>(a, s);
-    case 2: return w ? launch_stream<DT, 2, 256, SEL, MODE>(a, s) : launch_stream<DT, 2, 128, SEL, MODE>(a, s);
-    case 3: return w ? launch_stream<DT, 3, 256, SEL, MODE>(a, s) : launch_stream<DT, 3, 128, SEL, MODE>(a, s);
-    case 4: return w ? launch_stream<DT, 4, 256, SEL, MODE>(a, s) : launch_stream<DT, 4, 128, SEL, MODE>(a, s);
-    case 5: return w ? launch_stream<DT, 5, 256, SEL, MODE>(a, s) : launch_stream<DT, 5, 128, SEL, MODE>(a, s);
-    case 8: return w ? launch_stream<DT, 8, 256, SEL, MODE>(a, s) : launch_stream<DT, 8, 128, SEL, MODE>(a, s);
-    case 10: return w ? launch_stream<DT, 10, 256, SEL, MODE>(a, s) : launch_stream<DT, 10, 128, SEL, MODE>(a, s);
-    case 16: return w ? launch_stream<DT, 16, 256, SEL, MODE>(a, s) : launch_stream<DT, 16, 128, SEL, MODE>(a, s);
+    case 1: return launch_stream_w<DT, 1, SEL, MODE>(a, s);
+    case 2: return launch_stream_w<DT, 2, SEL, MODE>(a, s);
+    case 3: return launch_stream_w<DT, 3, SEL, MODE>(a, s);
+    case 4: return launch_stream_w<DT, 4, SEL, MODE>(a, s);
+    case 5: return launch_stream_w<DT, 5, SEL, MODE>(a, s);
+    case 8: return launch_stream_w<DT, 8, SEL, MODE>(a, s);
+    case 10: return launch_stream_w<DT, 10, SEL, MODE>(a, s);
+    case 16: return launch_stream_w<DT, 16, SEL, MODE>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -38,7 +38,7 @@ def test_fast_single_sweep(dev, shape, r):
     img = synth.rectangles(shape[1], shape[2], 6, 0.05, rng, C=shape[0])
     x = _gpu(img, dev)
     ref = None
-    for g in (0, 1, 2, 3, 4, 5, 6):
+    for g in (0, 1, 2, 3, 4, 5, 6, 7):
         with plan(g, 1):
             y = osbf.forward_fast(x, r, 1)
         if ref is None:

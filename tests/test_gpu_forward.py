@@ -15,7 +15,7 @@ from tests.parity import check_sweep_planes, crop_check, replay_check_planes, ta
 
 pytestmark = pytest.mark.gpu
 
-TILES = [0, 1, 2, 3, 4, 5, 6]
+TILES = [0, 1, 2, 3, 4, 5, 6, 7]
 
 
 class plan:

@@ -1,5 +1,5 @@
-"""GPU parity of the row-streaming forward kernel (geometries 5 and 6: strips
-of 128 or 256 lanes walking down chunks of rows, one sweep per launch; the
+"""GPU parity of the row-streaming forward kernel (geometries 5, 6 and 7: strips
+of 128, 192 or 256 lanes walking down chunks of rows, one sweep per launch; the
 exact filter, the fast approximation and the box filter).
 
 Its running sums restart at the same image positions as in the tiled kernels
@@ -40,7 +40,7 @@ def _plan_shape(planes, H, W, r, T=1):
     return p["tile"][0], p["tile"][1], p["fused"], p["launches"]
 
 
-@pytest.mark.parametrize("geom", [5, 6])
+@pytest.mark.parametrize("geom", [5, 6, 7])
 @pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8, 10, 16])
 def test_stream_equals_tiled(dev, geom, r):
     rng = np.random.default_rng(700 + 10 * r + geom)
@@ -52,7 +52,8 @@ def test_stream_equals_tiled(dev, geom, r):
         for rows in (0, STEP[r], 3 * STEP[r] + 1):
             with plan(geom, 1, rows):
                 tw, th, k, _ = _plan_shape(*shape, r)
-                assert k == 1 and tw % r == 0 and th % STEP[r] == 0 and th >= STEP[r]
+                # rows 0: balanced over the device's resident workgroups (tile_h 0)
+                assert k == 1 and tw % r == 0 and th % STEP[r] == 0 and (th >= STEP[r] or rows == 0)
                 y, sel = osbf.forward(x, r, 2, return_sel=True)
                 y2 = osbf.forward(x, r, 2)
             assert torch.equal(y, want) and torch.equal(sel, wsel), (shape, rows)
@@ -85,7 +86,7 @@ def test_stream_full_size_equals_tiled(dev):
     x = torch.from_numpy(synth.workload_rgb()).to(dev)
     with plan(3, 1):
         want = osbf.forward(x, 10, 3)
-    for geom in (5, 6):
+    for geom in (5, 6, 7):
         with plan(geom, 1):
             assert torch.equal(osbf.forward(x, 10, 3), want)
 
@@ -99,7 +100,7 @@ def test_stream_modes_equal_tiled(dev, r):
     with plan(1, 1):
         f = osbf.forward_fast(x, r, 3)
         b = osbf.box_forward(x, r, 3)
-    for geom in (5, 6):
+    for geom in (5, 6, 7):
         with plan(geom, 1):
             assert torch.equal(osbf.forward_fast(x, r, 3), f)
             assert torch.equal(osbf.box_forward(x, r, 3), b)
