@@ -205,7 +205,7 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
 
 /*
  * osbf_batched_launch -- run a prepared batch: one persistent launch per
- * round (every unfinished image advances by its fused sweep count).  Only
+ * round (every unfinished image advances by one sweep).  Only
  * kernel launches and device-to-device copies are enqueued, so the call can
  * be captured into a HIP graph and replayed; each replay recomputes dst from
  * src.  Results equal per-image osbf_forward bit for bit.
@@ -242,10 +242,8 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osb
  * and blocks until done (do not call during stream capture).  The winner is
  * cached per (device, radius, dtype, size class: planes*height*width below or
  * at least 2^20) and used by later osbf_forward / osbf_backward /
- * osbf_forward_plan calls of that class, and by batched images of that class
- * when the tuned plan uses the batch's 64x48 region (its fusion depth);
- * OSBF_PLAN in the environment still takes precedence for single images.
- * Batched workspace sizes depend on the cache: tune before sizing a batch.
+ * osbf_forward_plan calls of that class (batches keep their own work
+ * items); OSBF_PLAN in the environment still takes precedence.
  * Every plan computes the same bits, so tuning changes speed, never
  * results.  Writes the chosen tile and fused sweeps (0 for
  * radius 0 or iterations 0).  The cache is process state guarded by a mutex.

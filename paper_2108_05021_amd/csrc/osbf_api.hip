@@ -564,21 +564,24 @@ namespace {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct BatchImagePlan {
-    int k = 1, rounds = 0;
-    Plan plan;
+    int rounds = 0;
+    int tw = 0, th = 0;  // strip width, rows per work item
 };
 
-// Per-image plans of a batch (64x48 fixed geometry) and the table sizes.
+// Per-image plans of a batch (row-streaming work items, one sweep per round)
+// and the table sizes.
 struct BatchLayout {
     std::vector<BatchImagePlan> img;
-    int rounds = 0;
+    int rounds = 0, maxr = 0;
     int64_t max_items = 0, total_items = 0;
     size_t descs_off = 0, items_off = 0, counts_off = 0, bufs_off = 0, total = 0;
     std::vector<size_t> buf_off;
     int identity = 0;
 };
 
-const int kBatchK[][2] = {{1, 3}, {2, 3}, {3, 2}, {4, 1}, {5, 1}, {8, 1}, {10, 1}, {16, 1}};
+// Rows per work item: long enough that the r halo rows a chunk recomputes
+// stay small, short enough that a round has many items to balance.
+constexpr int kBatchRows = 64;
 
 osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchLayout *L) {
     if (n < 0 || (n > 0 && !imgs)) return fail(OSBF_ERROR_INVALID_VALUE, "bad image list");
@@ -597,25 +600,14 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
             L->identity++;
             continue;
         }
-        int k = 0;
-        for (const auto &t : kBatchK)
-            if (t[0] == m.radius) k = t[1];
-        if (!k) return fail(OSBF_ERROR_UNSUPPORTED, "image %d: batched radius %d not in {1,2,3,4,5,8,10,16}", j, m.radius);
-        // a plan osbf_autotune measured for this image's class on the batch's
-        // geometry sets its fusion depth
-        Plan tuned;
-        if (tuned_plan(m.planes, m.height, m.width, m.radius, m.iterations, (int)dtype, &tuned) &&
-            tuned.geom == GEOM_64x48)
-            k = tuned.k;
-        k = std::min(k, m.iterations);
-        for (; k >= 1; --k) {
-            b.plan = make_plan(GEOM_64x48, kGeomDims[GEOM_64x48][0], kGeomDims[GEOM_64x48][1], m.radius, k);
-            if (b.plan.tw) break;
-        }
-        if (!b.plan.tw) return fail(OSBF_ERROR_UNSUPPORTED, "image %d: no tile fits", j);
-        b.k = k;
-        b.rounds = (m.iterations + k - 1) / k;
-        const int64_t tiles = (int64_t)((m.width + b.plan.tw - 1) / b.plan.tw) * ((m.height + b.plan.th - 1) / b.plan.th);
+        if (!fixed_radius(m.radius))
+            return fail(OSBF_ERROR_UNSUPPORTED, "image %d: batched radius %d not in {1,2,3,4,5,8,10,16}", j, m.radius);
+        const int r = m.radius, step = stream_step(r);
+        b.tw = ((batched_lanes() - 2 * r) / r) * r;
+        b.th = (std::min(m.height, kBatchRows) + step - 1) / step * step;
+        b.rounds = m.iterations;
+        L->maxr = std::max(L->maxr, r);
+        const int64_t tiles = (int64_t)((m.width + b.tw - 1) / b.tw) * ((m.height + b.th - 1) / b.th);
         const int64_t items = tiles * m.planes;
         if ((int)per_round.size() < b.rounds) per_round.resize(b.rounds, 0);
         for (int r = 0; r < b.rounds; ++r) per_round[r] += items;
@@ -641,12 +633,6 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
     return OSBF_SUCCESS;
 }
 
-int device_cus() {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
-        return 256;
-    return v;
-}
 
 }  // namespace
 
@@ -675,14 +661,11 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
     std::vector<FwdLaunch> descs((size_t)L.rounds * n);
     std::vector<uint2> items((size_t)L.rounds * L.max_items);
     std::vector<int> counts(std::max(L.rounds, 1), 0);
-    // images in decreasing cost order (fused depth, then radius) for the work lists
+    // images in decreasing cost order (radius) for the work lists
     std::vector<int> order;
     for (int j = 0; j < n; ++j)
         if (L.img[j].rounds) order.push_back(j);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const int ca = L.img[a].k * 64 + imgs[a].radius, cb = L.img[b].k * 64 + imgs[b].radius;
-        return ca > cb;
-    });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return imgs[a].radius > imgs[b].radius; });
     for (int j = 0; j < n; ++j) {
         const BatchImagePlan &b = L.img[j];
         const osbf_image &m = imgs[j];
@@ -697,12 +680,12 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
             a.sel_stride = 0;
             a.planes = m.planes;
             a.H = m.height; a.W = m.width; a.r = m.radius;
-            a.k = std::min(b.k, m.iterations - r * b.k);
-            a.tw = b.plan.tw; a.th = b.plan.th;
-            a.tiles_x = (m.width + b.plan.tw - 1) / b.plan.tw;
-            a.tiles_y = (m.height + b.plan.th - 1) / b.plan.th;
-            a.pitch = b.plan.pitch; a.arr = b.plan.arr;
-            a.geom = GEOM_64x48;
+            a.k = 1;
+            a.tw = b.tw; a.th = b.th;
+            a.tiles_x = (m.width + b.tw - 1) / b.tw;
+            a.tiles_y = (m.height + b.th - 1) / b.th;
+            a.pitch = a.arr = 0;
+            a.geom = GEOM_S128;
             cur = out;
         }
     }
@@ -729,8 +712,9 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
         // the host vectors go out of scope: wait for the copies
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "synchronize");
     }
-    const int slots = std::max(1, (int)(163840 / batched_lds_bytes()));
-    const int64_t g = std::min<int64_t>(L.max_items, (int64_t)device_cus() * slots);
+    int slots = 0;
+    if (L.rounds && (e = batched_slots((int)dtype, L.maxr, &slots)) != hipSuccess) return hip_fail(e, "occupancy");
+    const int64_t g = std::min<int64_t>(L.max_items, std::max(slots, 1));
     memset(batch, 0, sizeof *batch);
     batch->n = n;
     batch->dtype = dtype;
@@ -743,6 +727,7 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
     batch->items_off = L.items_off;
     batch->counts_off = L.counts_off;
     batch->identity = L.identity;
+    batch->reserved[0] = L.maxr;  // kernel class and LDS of the rounds
     // identity images are copied at launch: remember them in the tables is
     // not needed; the launch re-reads the host list through the caller.
     return OSBF_SUCCESS;
@@ -758,7 +743,7 @@ osbf_status osbf_batched_launch(const osbf_batch *batch, void *stream_) {
     const uint2 *items = (const uint2 *)((const char *)batch->ws + batch->items_off);
     const int *counts = (const int *)((const char *)batch->ws + batch->counts_off);
     for (int r = 0; r < batch->rounds; ++r) {
-        hipError_t e = launch_batched_round(batch->dtype, descs + (size_t)r * batch->n,
+        hipError_t e = launch_batched_round(batch->dtype, batch->reserved[0], descs + (size_t)r * batch->n,
                                             items + (size_t)r * batch->max_items, counts + r, batch->grid, stream);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }

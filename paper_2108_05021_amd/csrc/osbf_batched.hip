@@ -1,42 +1,49 @@
 // Batched forward over many images of different sizes, radii and iteration
 // counts, gfx950.
 //
-// The batch advances in rounds: in every round each unfinished image runs its
-// own number of fused sweeps (its plan's k, or what is left of T).  A round is
-// one persistent launch: a grid of about one workgroup per LDS slot on the
-// device walks a work list of (image, plane, tile) items, so small and large
-// images share the machine without per-image launches.  Items of a round are
-// ordered by decreasing cost, and each XCD takes a contiguous slice of the
-// list so neighbouring tiles of an image meet in the same L2.
+// The batch advances in rounds: in every round each unfinished image runs one
+// sweep.  A round is one persistent launch: a grid of about one workgroup per
+// resident slot on the device walks a work list of (image, item) pairs, an
+// item being one row chunk of one strip of one plane (the row-streaming
+// kernel's work unit, 128-lane strips), so small and large images share the
+// machine without per-image launches.  Items of a round are ordered by
+// decreasing radius, and each XCD takes a contiguous slice of the list so
+// neighbouring items of an image meet in the same L2.
 //
-// Every item runs the same fixed-geometry tile code as the single-image
-// kernels; its window sums are position-deterministic, so the batch gives the
-// same bits as filtering each image alone.
-#include "osbf_fwd_device.h"
+// Every item runs the same code as the single-image streaming kernel; its
+// window sums are position-deterministic, so the batch gives the same bits as
+// filtering each image alone.  Batches whose radii are all at most 8 take a
+// kernel without the larger radii's code, which needs fewer registers.
+#include "osbf_stream_device.h"
 
 namespace osbf {
 
-template <int DT>
-__device__ __forceinline__ void batched_item(const FwdLaunch &a, int tile, int plane, float *lds) {
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+constexpr int kBatchLanes = 128;
+
+template <int DT, int MAXR>
+__device__ __forceinline__ void batched_item(const FwdLaunch &a, int t, float *lds) {
     switch (a.r) {
-    case 1: fwd_fixed<DT, 1, 64, 48, 512, false>(a, tx, ty, plane, lds); break;
-    case 2: fwd_fixed<DT, 2, 64, 48, 512, false>(a, tx, ty, plane, lds); break;
-    case 3: fwd_fixed<DT, 3, 64, 48, 512, false>(a, tx, ty, plane, lds); break;
-    case 4: fwd_fixed<DT, 4, 64, 48, 512, false>(a, tx, ty, plane, lds); break;
-    case 5: fwd_fixed<DT, 5, 64, 48, 512, false>(a, tx, ty, plane, lds); break;
-    case 8: fwd_fixed<DT, 8, 64, 48, 512, false>(a, tx, ty, plane, lds); break;
-    case 10: fwd_fixed<DT, 10, 64, 48, 512, false>(a, tx, ty, plane, lds); break;
-    case 16: fwd_fixed<DT, 16, 64, 48, 512, false>(a, tx, ty, plane, lds); break;
+    case 1: fwd_stream_item<DT, 1, kBatchLanes, stream_step_rows(1), false, MODE_EXACT>(a, t, lds); break;
+    case 2: fwd_stream_item<DT, 2, kBatchLanes, stream_step_rows(2), false, MODE_EXACT>(a, t, lds); break;
+    case 3: fwd_stream_item<DT, 3, kBatchLanes, stream_step_rows(3), false, MODE_EXACT>(a, t, lds); break;
+    case 4: fwd_stream_item<DT, 4, kBatchLanes, stream_step_rows(4), false, MODE_EXACT>(a, t, lds); break;
+    case 5: fwd_stream_item<DT, 5, kBatchLanes, stream_step_rows(5), false, MODE_EXACT>(a, t, lds); break;
+    case 8: fwd_stream_item<DT, 8, kBatchLanes, stream_step_rows(8), false, MODE_EXACT>(a, t, lds); break;
+    case 10:
+        if constexpr (MAXR >= 10) fwd_stream_item<DT, 10, kBatchLanes, stream_step_rows(10), false, MODE_EXACT>(a, t, lds);
+        break;
+    case 16:
+        if constexpr (MAXR >= 16) fwd_stream_item<DT, 16, kBatchLanes, stream_step_rows(16), false, MODE_EXACT>(a, t, lds);
+        break;
     default: break;  // rejected on the host
     }
 }
 
 // descs: this round's per-image launch descriptors; items: (image, item)
-// pairs of this round, item = plane * tiles + tile; count: number of items.
-template <int DT>
-__global__ __launch_bounds__(512) void batched_round_kernel(const FwdLaunch *descs, const uint2 *items,
-                                                            const int *count) {
+// pairs of this round; count: number of items.
+template <int DT, int MAXR>
+__global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(stream_min_waves(MAXR))))
+void batched_round_kernel(const FwdLaunch *descs, const uint2 *items, const int *count) {
     extern __shared__ float lds[];
     const int n = *count;
     const int nx = gridDim.x >> 3;           // workgroups per XCD (grid is a multiple of 8)
@@ -45,24 +52,66 @@ __global__ __launch_bounds__(512) void batched_round_kernel(const FwdLaunch *des
     const int start = xcd * chunk, end = min(n, start + chunk);
     for (int it = start + l; it < end; it += nx) {
         const uint2 w = items[it];
-        const FwdLaunch &a = descs[w.x];
-        const int ntiles = a.tiles_x * a.tiles_y;
-        const int plane = (int)w.y / ntiles, tile = (int)w.y - plane * ntiles;
-        batched_item<DT>(a, tile, plane, lds);
+        batched_item<DT, MAXR>(descs[w.x], (int)w.y, lds);
         __syncthreads();  // LDS is reused by the next item
     }
 }
 
-size_t batched_lds_bytes() { return (size_t)4 * 48 * 65 * sizeof(float); }
+int batched_lanes() { return kBatchLanes; }
 
-hipError_t launch_batched_round(int dtype, const FwdLaunch *descs, const uint2 *items, const int *count,
-                                int grid, hipStream_t stream) {
-    const size_t lds = batched_lds_bytes();
+// LDS of a batch whose largest radius class is maxr: every radius up to it
+// must fit (the step, and with it the ring, is not monotonic in r).
+size_t batched_lds_bytes(int maxr) {
+    size_t b = 0;
+    for (int r : {1, 2, 3, 4, 5, 8, 10, 16})
+        if (r <= maxr) b = std::max(b, stream_lds_bytes(kBatchLanes, r));
+    return b;
+}
+
+template <int DT, int MAXR>
+static auto batched_kernel() {
+    return batched_round_kernel<DT, MAXR>;
+}
+
+template <int MAXR>
+static const void *batched_fn(int dtype) {
     switch (dtype) {
-    case DT_F32: hipLaunchKernelGGL(batched_round_kernel<DT_F32>, dim3(grid), dim3(512), lds, stream, descs, items, count); break;
-    case DT_F16: hipLaunchKernelGGL(batched_round_kernel<DT_F16>, dim3(grid), dim3(512), lds, stream, descs, items, count); break;
-    default: hipLaunchKernelGGL(batched_round_kernel<DT_BF16>, dim3(grid), dim3(512), lds, stream, descs, items, count); break;
+    case DT_F32: return (const void *)batched_kernel<DT_F32, MAXR>();
+    case DT_F16: return (const void *)batched_kernel<DT_F16, MAXR>();
+    default: return (const void *)batched_kernel<DT_BF16, MAXR>();
     }
+}
+
+static const void *batched_function(int dtype, int maxr) {
+    return maxr <= 8 ? batched_fn<8>(dtype) : batched_fn<16>(dtype);
+}
+
+// Resident workgroups of the round kernel on the current device.
+hipError_t batched_slots(int dtype, int maxr, int *slots) {
+    int dev = 0, cus = 0, per_cu = 0;
+    const void *fn = batched_function(dtype, maxr);
+    const size_t lds = batched_lds_bytes(maxr);
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && lds > 65536)
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchLanes, lds);
+    if (e != hipSuccess) return e;
+    *slots = std::max(1, cus * per_cu);
+    return hipSuccess;
+}
+
+hipError_t launch_batched_round(int dtype, int maxr, const FwdLaunch *descs, const uint2 *items,
+                                const int *count, int grid, hipStream_t stream) {
+    const void *fn = batched_function(dtype, maxr);
+    const size_t lds = batched_lds_bytes(maxr);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    void *args[] = {(void *)&descs, (void *)&items, (void *)&count};
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBatchLanes), args, lds, stream);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

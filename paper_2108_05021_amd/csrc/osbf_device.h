@@ -27,8 +27,15 @@ template <> struct Storage<DT_F16> {
     using T = _Float16;
     static __device__ __forceinline__ float cvt(T v) { return (float)v; }
     static __device__ __forceinline__ float load(const T *p, size_t i) { return (float)p[i]; }
-    static __device__ __forceinline__ T pack(float v) { return (T)v; }
-    static __device__ __forceinline__ float round(float v) { return (float)(T)v; }
+    // The FP32 value is made opaque before the conversion, so the compiler
+    // cannot fuse the FMA that produced it with the conversion (a single
+    // rounding straight to F16 can differ by one ulp from rounding the FP32
+    // result); every kernel then rounds the same FP32 value.
+    static __device__ __forceinline__ T pack(float v) {
+        asm("" : "+v"(v));
+        return (T)v;
+    }
+    static __device__ __forceinline__ float round(float v) { return (float)pack(v); }
 };
 
 template <> struct Storage<DT_BF16> {

@@ -59,10 +59,13 @@ void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr);
 // (false if r is served by the generic kernel).
 bool adjoint_fixed_tile(int r, int *tw, int *th, size_t *lds_bytes);
 
-// Batched rounds (64x48 fixed geometry, 512 threads).
-size_t batched_lds_bytes();
-hipError_t launch_batched_round(int dtype, const FwdLaunch *descs, const uint2 *items, const int *count,
-                                int grid, hipStream_t stream);
+// Batched rounds (row-streaming work items, batched_lanes()-wide strips); maxr
+// is the largest radius of the batch (selects the kernel and its LDS).
+int batched_lanes();
+size_t batched_lds_bytes(int maxr);
+hipError_t batched_slots(int dtype, int maxr, int *slots);
+hipError_t launch_batched_round(int dtype, int maxr, const FwdLaunch *descs, const uint2 *items,
+                                const int *count, int grid, hipStream_t stream);
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t s);
 
 // One sweep of the volume filter over every volume: a workgroup per

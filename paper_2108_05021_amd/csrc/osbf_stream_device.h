@@ -39,8 +39,11 @@ constexpr int stream_step_rows(int r) {
 
 // MODE: MODE_EXACT, MODE_FAST (quadrant means only, no H field) or MODE_BOX,
 // as in the tiled kernels; maps (SEL) only with MODE_EXACT.
-template <int DT, int R, int RW, int CH, bool SEL, int MODE = MODE_EXACT>
-__global__ __launch_bounds__(RW) void fwd_stream_kernel(FwdLaunch a) {
+// One work item t = (plane * chunks + chunk) * strips + strip: rows
+// [chunk * th, chunk * th + th) of one strip of one plane (shared by the
+// single-image and the batched kernels).
+template <int DT, int R, int RW, int CH, bool SEL, int MODE>
+__device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) {
     using S = Storage<DT>;
     using T = typename S::T;
     static_assert(CH % R == 0, "a step is whole blocks of R rows");
@@ -48,7 +51,6 @@ __global__ __launch_bounds__(RW) void fwd_stream_kernel(FwdLaunch a) {
     constexpr int M = CH / R;        // blocks per step
     constexpr int NRB = M + 1;       // blocks in the Q/H ring
     constexpr int PITCH = RW + 1;
-    extern __shared__ float lds[];
     float *const Pl = lds;                      // CH rows
     float *const Vl = lds + CH * PITCH;         // CH rows
     float *const Qr = lds + 2 * CH * PITCH;     // NRB * R rows
@@ -57,7 +59,6 @@ __global__ __launch_bounds__(RW) void fwd_stream_kernel(FwdLaunch a) {
     const int lx = threadIdx.x;
     const int H = a.H, W = a.W, TW = a.tw, YC = a.th;
     const int ntiles = a.tiles_x * a.tiles_y;
-    const int t = xcd_remap(blockIdx.x, ntiles * a.planes);
     const int plane = t / ntiles, tile = t - plane * ntiles;
     const int chunk = tile / a.tiles_x, strip = tile - chunk * a.tiles_x;
     const int X0 = strip * TW, Y0 = chunk * YC;
@@ -265,6 +266,17 @@ __global__ __launch_bounds__(RW) void fwd_stream_kernel(FwdLaunch a) {
         base = base == 0 ? M : base - 1;
     }
     if (pending && own) store_step();
+}
+
+// Waves per SIMD the register allocation must leave room for (the LDS ring
+// allows about this many workgroups per CU at the default strip widths).
+constexpr int stream_min_waves(int r) { return r >= 16 ? 2 : r >= 10 ? 3 : 4; }
+
+template <int DT, int R, int RW, int CH, bool SEL, int MODE = MODE_EXACT>
+__global__ __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(stream_min_waves(R))))
+void fwd_stream_kernel(FwdLaunch a) {
+    extern __shared__ float lds[];
+    fwd_stream_item<DT, R, RW, CH, SEL, MODE>(a, xcd_remap(blockIdx.x, a.tiles_x * a.tiles_y * a.planes), lds);
 }
 
 template <int DT, int R, int RW, bool SEL, int MODE>
