@@ -275,17 +275,22 @@ hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, u
     return hipSuccess;
 }
 
-// Tile of the adjoint kernel: the largest multiple of r whose 2r-grown
-// region fits the smallest of 64/80/96/128 pixels that leaves a tile, within
-// the device's LDS.
-// Adjoint tiling: the fixed-geometry kernel for its radii (OSBF_ADJOINT=
-// generic forces the generic kernel), else the smallest square region of the
-// generic kernel that fits the device's LDS.
+// Adjoint kernel choice: the row-streaming kernel for its radii, then the
+// fixed-geometry tiled kernel, then the smallest square region of the generic
+// kernel that fits the device's LDS.  OSBF_ADJOINT=fixed or generic forces
+// the tiled kernels (tests compare all of them bit for bit).
 bool adjoint_tile(int r, BwdLaunch *b) {
     const char *env = getenv("OSBF_ADJOINT");
     const bool force_generic = env && strcmp(env, "generic") == 0;
+    const bool force_fixed = env && strcmp(env, "fixed") == 0;
     b->fixed = 0;
     size_t fixed_lds = 0;
+    if (!force_generic && !force_fixed && adjoint_stream_tile(r, &b->tw, &b->th, &fixed_lds) &&
+        fixed_lds <= lds_limit()) {
+        b->fixed = 2;
+        b->pitch = b->arr = 0;
+        return true;
+    }
     if (!force_generic && adjoint_fixed_tile(r, &b->tw, &b->th, &fixed_lds) && fixed_lds <= lds_limit()) {
         b->fixed = 1;
         b->pitch = b->arr = 0;

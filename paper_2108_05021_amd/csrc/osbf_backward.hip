@@ -413,6 +413,242 @@ static hipError_t launch_adjoint_fixed(const BwdLaunch &a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Row-streaming adjoint.  A workgroup of RW lanes owns a strip of TW output
+// columns and a chunk of output rows of one plane (lane = region column
+// X0 - 2R + lane) and walks down the chunk's q rows CH = M*R at a time.  Per
+// step (q rows [s, s + CH)): the lane's gv and selection rows [s - R, s + CH
+// + R) live in registers (2R carried over, CH loaded one step ahead); the
+// vertical pass forms VL+VF, VR+VF and VF there, block by block, and writes
+// them to LDS; the horizontal pass (each lane's (row, column block) items,
+// the same every step) forms Gpad over VF; then each lane folds and stores
+// the output rows these q rows complete.
+// VF/Gpad is double-buffered by step parity, so a step costs two barriers.
+// The block anchors, the FP32 operations and the fold order are those of the
+// tiled adjoint kernels, so the results are bit-identical to theirs.
+template <int R, int RW, int M>
+__global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
+    constexpr int PITCH = RW + 1, CH = M * R;
+    extern __shared__ float lds[];
+    float *const HL = lds;                   // CH rows
+    float *const HR = lds + CH * PITCH;      // CH rows
+    float *const VF0 = lds + 2 * CH * PITCH; // 2 x CH rows: VF, then Gpad
+    const int lx = threadIdx.x;
+    const int H = a.H, W = a.W, TW = a.tw, YC = a.th;
+    const int ntiles = a.tiles_x * a.tiles_y;
+    const int t = xcd_remap(blockIdx.x, ntiles * a.planes);
+    const int plane = t / ntiles, tile = t - plane * ntiles;
+    const int chunk = tile / a.tiles_x, strip = tile - chunk * a.tiles_x;
+    const int X0 = strip * TW, Y0 = chunk * YC;
+    const int ox = X0 - 2 * R;  // image column of LDS column 0
+    const int x = ox + lx;
+    const size_t plane_off = (size_t)plane * H * W;
+    const float *gn = a.gnext + plane_off;
+    const uint8_t *sl = a.sel + plane_off;
+    float *gout = a.g + plane_off;
+
+    // q region (the chunk grown by R beyond every image edge it touches) and
+    // the F columns it reads
+    const int qx0 = X0 == 0 ? -R : X0, qx1 = X0 + TW >= W ? W + R : X0 + TW;
+    const int qy0 = Y0 == 0 ? -R : Y0, qy1 = Y0 + YC >= H ? H + R : Y0 + YC;
+    const bool vcol = x >= qx0 - R && x < qx1 + R;
+    const bool xin = x >= 0 && x < W;
+    const int xc = min(max(x, 0), W - 1);
+    const int xe = min(W, X0 + TW);
+    const bool own = x >= X0 && x < xe;
+    const int fxa = x == 0 ? -R : x, fxb = x == W - 1 ? W - 1 + R : x;  // fold columns
+    const float inv_h = 1.0f / (float)((R + 1) * (2 * R + 1));
+    const float inv_q = 1.0f / (float)((R + 1) * (R + 1));
+
+    // this lane's horizontal items: (row, block of R columns), rows of one
+    // block of R rows consecutive, row fastest; CH * nb <= M * (TW + 2R) <=
+    // M * RW, so M items per lane cover all
+    const int nb = (qx1 - qx0 + R - 1) / R;
+    int it_t[M], it_x0[M];
+    bool it_ok[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int it = lx + k * RW;
+        const int m = it / (R * nb), rem = it - m * (R * nb);
+        const int b = rem / R;
+        it_ok[k] = it < CH * nb;
+        it_t[k] = m * R + (rem - b * R);
+        it_x0[k] = qx0 + b * R;
+    }
+
+    float g[CH + 2 * R];  // gv of rows [s - R, s + CH + R) of this lane's column
+    int s_[CH + 2 * R];   // their selections (0 outside the image)
+    float graw[CH];
+    uint8_t sraw[CH];
+    auto load_rows = [&](int y0) {  // rows [y0, y0 + CH), clamped into the image
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const size_t gi = (size_t)min(max(y0 + j, 0), H - 1) * W + xc;
+            graw[j] = gn[gi];
+            sraw[j] = sl[gi];
+        }
+    };
+    auto convert = [&](int j, int yy, float gr, int sr) {
+        const bool in = xin && yy >= 0 && yy < H;
+        s_[j] = in ? sr : 0;
+        g[j] = in ? gr * (s_[j] >= 4 ? inv_q : inv_h) : 0.f;
+    };
+    // rows [qy0 - R, qy0 + R), then the first lookahead rows
+    load_rows(qy0 - R);
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) {
+        if (j < CH) {
+            convert(j, qy0 - R + j, graw[j], sraw[j]);
+        } else {  // CH < 2R (M = 1): the rest of the 2R rows
+            const size_t gi = (size_t)min(max(qy0 - R + j, 0), H - 1) * W + xc;
+            convert(j, qy0 - R + j, gn[gi], sl[gi]);
+        }
+    }
+    load_rows(qy0 + R);
+
+    const int nsteps = (qy1 - qy0 + CH - 1) / CH;
+    float acc = 0.f;  // fold of the output row being accumulated
+    for (int n = 0; n < nsteps; ++n) {
+        const int s0 = qy0 + n * CH;
+        float *const VF = VF0 + (n & 1) * CH * PITCH;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) convert(2 * R + j, s0 + R + j, graw[j], sraw[j]);
+        if (n + 1 < nsteps) load_rows(s0 + CH + R);
+        // vertical pass: the operations of adjoint_fixed_kernel's block, for
+        // the M blocks of R rows of this step
+#pragma unroll
+        for (int mb = 0; mb < M; ++mb) {
+            const int y0 = s0 + mb * R;
+            if (!vcol || y0 >= qy1) continue;  // the row condition is uniform
+            const int *s = s_ + mb * R;        // rows [y0 - R, y0 + 2R)
+            const float *gb = g + mb * R;
+            float u1 = pick(M_C1, s[0], gb[0]), u3 = pick(M_C3, s[0], gb[0]), ud = pick(M_FD, s[0], gb[0]);
+#pragma unroll
+            for (int j = 1; j <= R; ++j) {
+                u1 += pick(M_C1, s[j], gb[j]);
+                u3 += pick(M_C3, s[j], gb[j]);
+                ud += pick(M_FD, s[j], gb[j]);
+            }
+            float d2 = pick(M_C2, s[R], gb[R]), d4 = pick(M_C4, s[R], gb[R]), du = pick(M_FU, s[R], gb[R]);
+#pragma unroll
+            for (int j = R + 1; j <= 2 * R; ++j) {
+                d2 += pick(M_C2, s[j], gb[j]);
+                d4 += pick(M_C4, s[j], gb[j]);
+                du += pick(M_FU, s[j], gb[j]);
+            }
+            auto emit = [&](int tt) {
+                const int j = R + tt;
+                const float vf = ud + du;
+                const float vl = u1 + d2 - pick(M_FR, s[j], gb[j]);
+                const float vr = u3 + d4 - pick(M_FL, s[j], gb[j]);
+                const int o = (mb * R + tt) * PITCH + lx;
+                HL[o] = vl + vf;
+                HR[o] = vr + vf;
+                VF[o] = vf;
+            };
+            emit(0);
+#pragma unroll
+            for (int tt = 1; tt < R; ++tt) {
+                if (y0 + tt < qy1) {  // uniform
+                    const int nn = R + tt, od = tt - 1, n2 = 2 * R + tt, od2 = R + tt - 1;
+                    u1 += pick(M_C1, s[nn], gb[nn]) - pick(M_C1, s[od], gb[od]);
+                    u3 += pick(M_C3, s[nn], gb[nn]) - pick(M_C3, s[od], gb[od]);
+                    ud += pick(M_FD, s[nn], gb[nn]) - pick(M_FD, s[od], gb[od]);
+                    d2 += pick(M_C2, s[n2], gb[n2]) - pick(M_C2, s[od2], gb[od2]);
+                    d4 += pick(M_C4, s[n2], gb[n2]) - pick(M_C4, s[od2], gb[od2]);
+                    du += pick(M_FU, s[n2], gb[n2]) - pick(M_FU, s[od2], gb[od2]);
+                    emit(tt);
+                }
+            }
+        }
+        __syncthreads();
+
+        // horizontal pass: Gpad = Hl[HL] + Hr[HR] - VF over VF
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            if (!it_ok[k] || s0 + it_t[k] >= qy1) continue;
+            const int ro = it_t[k] * PITCH - ox;  // + image column
+            const int x0 = it_x0[k];
+            float hl[2 * R], hr[2 * R];
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) {
+                hl[i] = HL[ro + x0 - R + i];
+                hr[i] = HR[ro + min(x0 + i, qx1 + R - 1)];
+            }
+            float sl_ = hl[0], sr_ = hr[0];
+#pragma unroll
+            for (int i = 1; i <= R; ++i) sl_ += hl[i];
+#pragma unroll
+            for (int i = 1; i <= R; ++i) sr_ += hr[i];
+            VF[ro + x0] = sl_ + sr_ - VF[ro + x0];
+#pragma unroll
+            for (int tt = 1; tt < R; ++tt) {
+                if (x0 + tt < qx1) {
+                    sl_ += hl[R + tt] - hl[tt - 1];
+                    sr_ += hr[R + tt] - hr[tt - 1];
+                    VF[ro + x0 + tt] = sl_ + sr_ - VF[ro + x0 + tt];
+                }
+            }
+        }
+        __syncthreads();
+
+        // fold and store: q row qy belongs to output row clamp(qy); an output
+        // row whose clamp preimage (rows [ya, yb] x columns [fxa, fxb]) is
+        // more than the pixel sums it row by row, left to right, from 0
+        if (own) {
+#pragma unroll
+            for (int tt = 0; tt < CH; ++tt) {
+                const int qy = s0 + tt;
+                if (qy >= qy1) break;  // uniform
+                const int yo = min(max(qy, 0), H - 1);
+                const int ya = yo == 0 ? -R : yo, yb = yo == H - 1 ? H - 1 + R : yo;
+                const float *gp = VF + tt * PITCH - ox;  // + image column
+                if (ya == yb && fxa == fxb) {
+                    gout[(size_t)yo * W + x] = gp[x];
+                } else {
+                    if (qy == ya) acc = 0.f;
+                    for (int qx = fxa; qx <= fxb; ++qx) acc += gp[qx];
+                    if (qy == yb) gout[(size_t)yo * W + x] = acc;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) {
+            g[j] = g[CH + j];
+            s_[j] = s_[CH + j];
+        }
+    }
+}
+
+// Blocks of R rows per step of the streaming adjoint.  One block is fastest
+// at every compiled radius on MI355X (32x3x512x512): longer steps (8-10 rows
+// at r <= 5) need more registers and LDS and measured 10-25% slower.
+constexpr int adj_step_blocks(int) { return 1; }
+
+constexpr int kAdjStreamLanes = 128, kAdjStreamRows = 64;
+
+static size_t adjoint_stream_lds_bytes(int r) {
+    return (size_t)4 * adj_step_blocks(r) * r * (kAdjStreamLanes + 1) * sizeof(float);
+}
+
+bool adjoint_stream_tile(int r, int *tw, int *th, size_t *lds_bytes) {
+    if (!(r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 8 || r == 10 || r == 16)) return false;
+    *tw = ((kAdjStreamLanes - 4 * r) / r) * r;
+    const int step = adj_step_blocks(r) * r;
+    *th = (kAdjStreamRows + step - 1) / step * step;
+    *lds_bytes = adjoint_stream_lds_bytes(r);
+    return true;
+}
+
+template <int R>
+static hipError_t launch_adjoint_stream(const BwdLaunch &a, hipStream_t stream) {
+    const size_t lds = adjoint_stream_lds_bytes(R);
+    const int blocks = a.tiles_x * a.tiles_y * a.planes;
+    hipLaunchKernelGGL((adjoint_stream_kernel<R, kAdjStreamLanes, adj_step_blocks(R)>), dim3(blocks),
+                       dim3(kAdjStreamLanes), lds, stream, a);
+    return hipGetLastError();
+}
+
 // LDS layout of the adjoint kernel for a TW x TH tile: five arrays covering
 // the tile grown by 2r on every side.
 void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr) {
@@ -421,6 +657,19 @@ void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr) {
 }
 
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t stream) {
+    if (a.fixed == 2) {
+        switch (a.r) {
+            case 1: return launch_adjoint_stream<1>(a, stream);
+            case 2: return launch_adjoint_stream<2>(a, stream);
+            case 3: return launch_adjoint_stream<3>(a, stream);
+            case 4: return launch_adjoint_stream<4>(a, stream);
+            case 5: return launch_adjoint_stream<5>(a, stream);
+            case 8: return launch_adjoint_stream<8>(a, stream);
+            case 10: return launch_adjoint_stream<10>(a, stream);
+            case 16: return launch_adjoint_stream<16>(a, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (a.fixed) {
         switch (a.r) {
             case 1: return launch_adjoint_fixed<1, 64, 48>(a, stream);

@@ -51,10 +51,14 @@ struct BwdLaunch {
     int planes, H, W, r;
     int tw, th, tiles_x, tiles_y;
     int pitch, arr;       // LDS layout of the generic kernel (bwd_lds_layout)
-    int fixed;            // 1: fixed-geometry kernel (adjoint_fixed_tile)
+    int fixed;            // 1: fixed-geometry kernel (adjoint_fixed_tile);
+                          // 2: row-streaming kernel (tw strip, th rows per workgroup)
 };
 
 void bwd_lds_layout(int tw, int th, int r, int *pitch, int *arr);
+// Strip width, rows per workgroup and LDS bytes of the row-streaming adjoint
+// for radius r (false if r is not compiled for it).
+bool adjoint_stream_tile(int r, int *tw, int *th, size_t *lds_bytes);
 // Tile and LDS bytes of the fixed-geometry adjoint kernel for radius r
 // (false if r is served by the generic kernel).
 bool adjoint_fixed_tile(int r, int *tw, int *th, size_t *lds_bytes);

@@ -39,23 +39,28 @@ def test_single_adjoint_sweep(dev, shape, r):
 
 
 @pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8, 10, 16])
-@pytest.mark.parametrize("shape", [(2, 150, 197), (1, 1, 1), (1, 5, 300), (1, 300, 5), (1, 97, 64)])
-def test_fixed_adjoint_matches_generic(dev, monkeypatch, shape, r):
-    """The fixed-geometry adjoint and the generic one perform the same FP32
-    operations in the same order, so their gradients agree bit for bit."""
+@pytest.mark.parametrize("shape", [(2, 150, 197), (1, 1, 1), (1, 5, 300), (1, 300, 5), (1, 97, 64),
+                                   (1, 130, 250), (3, 66, 129)])
+def test_adjoint_kernels_agree(dev, monkeypatch, shape, r):
+    """The row-streaming adjoint (default), the fixed-geometry tiled one and
+    the generic one perform the same FP32 operations in the same order (same
+    block anchors, same fold order), so their gradients agree bit for bit."""
     rng = np.random.default_rng(30 + r)
     img = synth.voronoi(shape[1], shape[2], 6, 0.05, rng, C=shape[0])
     _, sel = osbf.forward(_gpu(img, dev), r, 1, return_sel=True)
     g = _gpu(rng.normal(size=img.shape), dev)
+    stream = osbf.backward(g, r, 1, sel=sel)
+    monkeypatch.setenv("OSBF_ADJOINT", "fixed")
     fixed = osbf.backward(g, r, 1, sel=sel)
     monkeypatch.setenv("OSBF_ADJOINT", "generic")
     generic = osbf.backward(g, r, 1, sel=sel)
     assert torch.equal(fixed, generic)
+    assert torch.equal(stream, fixed)
 
 
 def test_adjoint_full_size_properties(dev, monkeypatch):
     """32x3x512x512, r=3 (the fwd+bwd workload): one adjoint sweep conserves
-    the gradient's sum, matches the generic kernel bit for bit, and matches
+    the gradient's sum, matches the tiled kernels bit for bit, and matches
     the oracle on sampled 24x24 crops (each crop's outputs only depend on the
     gradient and maps within r of it, which the crop's oracle run sees)."""
     r = 3
@@ -69,6 +74,8 @@ def test_adjoint_full_size_properties(dev, monkeypatch):
     tot = float(g.double().sum())
     assert float(gx.double().sum()) == pytest.approx(tot, rel=1e-5, abs=1e-2)
     monkeypatch.setenv("OSBF_ADJOINT", "generic")
+    assert torch.equal(osbf.backward(g, r, 1, sel=sel), gx)
+    monkeypatch.setenv("OSBF_ADJOINT", "fixed")
     assert torch.equal(osbf.backward(g, r, 1, sel=sel), gx)
     s_all = sel[0]
     for p, y0, x0 in [(0, 0, 0), (17, 200, 333), (95, 512 - 24, 512 - 24), (50, 0, 300)]:
