@@ -130,10 +130,10 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 // the first).
 struct TunedShape { int r, geom, k, rows; };
 const TunedShape kTuned[] = {{1, GEOM_64x48, 3, 0},
-                             {2, GEOM_S192, 1, 32}, {2, GEOM_64x48, 2, 0},
+                             {2, GEOM_S256, 1, 0}, {2, GEOM_64x48, 2, 0},
                              {3, GEOM_S128, 1, 0}, {3, GEOM_64x48, 2, 0},
-                             {4, GEOM_S256, 1, 32}, {4, GEOM_64x48, 1, 0},
-                             {5, GEOM_S192, 1, 48}, {5, GEOM_64x60, 1, 0},
+                             {4, GEOM_S192, 1, 32}, {4, GEOM_64x48, 1, 0},
+                             {5, GEOM_S128, 1, 0}, {5, GEOM_64x60, 1, 0},
                              {8, GEOM_S192, 1, 0}, {8, GEOM_64x48, 1, 0},
                              {10, GEOM_S192, 1, 0}, {10, GEOM_64x60, 1, 0},
                              {16, GEOM_S192, 1, 0}, {16, GEOM_128x64, 1, 0}};

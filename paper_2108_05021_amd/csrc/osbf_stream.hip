@@ -4,9 +4,10 @@
 
 namespace osbf {
 
+// P and V staging (CH rows each), the Q ring (CH + r rows), H (CH rows).
 size_t stream_lds_bytes(int RW, int r) {
     const int ch = stream_step_rows(r);
-    return (size_t)(2 * ch + 2 * (ch + r)) * (RW + 1) * sizeof(float);
+    return (size_t)(4 * ch + r) * (RW + 1) * sizeof(float);
 }
 
 int stream_step(int r) { return stream_step_rows(r); }

@@ -10,8 +10,9 @@
 //     rows live in registers (the last r rows carry over to the next step);
 //     V is formed there in blocks of r rows anchored at multiples of r, with
 //     the FP32 operations of the tiled kernels;
-//   - the step's P and V rows go to LDS, where (row, block of r columns) work
-//     items form the row sums Q and H into a ring of CH + r rows;
+//   - the step's V rows and the P rows it evaluates go to LDS, where (row,
+//     block of r columns) work items form the row sums Q (into a ring of
+//     CH + r rows) and H (of the evaluated rows only);
 //   - the lane then evaluates rows [s - r, s + CH - r) of its column, whose
 //     windows reach down to row s + CH - 1.
 // Each step's stores are issued one step late, ahead of the next step's
@@ -51,10 +52,10 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
     constexpr int M = CH / R;        // blocks per step
     constexpr int NRB = M + 1;       // blocks in the Q/H ring
     constexpr int PITCH = RW + 1;
-    float *const Pl = lds;                      // CH rows
-    float *const Vl = lds + CH * PITCH;         // CH rows
-    float *const Qr = lds + 2 * CH * PITCH;     // NRB * R rows
-    float *const Hr = Qr + NRB * R * PITCH;     // NRB * R rows
+    float *const Pl = lds;                      // CH rows: P of the rows evaluated this step
+    float *const Vl = lds + CH * PITCH;         // CH rows: V of the step's new rows
+    float *const Qr = lds + 2 * CH * PITCH;     // NRB * R rows: ring of Q
+    float *const Hr = Qr + NRB * R * PITCH;     // CH rows: H of the rows evaluated this step
 
     const int lx = threadIdx.x;
     const int H = a.H, W = a.W, TW = a.tw, YC = a.th;
@@ -151,7 +152,7 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
         }
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            Pl[i * PITCH + lx] = pr[R + i];
+            Pl[i * PITCH + lx] = pr[i];  // rows [s - R, s - R + CH), evaluated this step
             Vl[i * PITCH + lx] = vr[R + i];
         }
         // the previous step's results, then the next step's loads
@@ -159,8 +160,10 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
         if (n + 1 < nsteps) load_step(s + CH);
         __syncthreads();
 
-        // Q and H of rows [s, s + CH) ∩ [Y0, yend), columns [xa, xend), into
-        // ring blocks base + 1 .. base + M
+        // Q of rows [s, s + CH) ∩ [Y0, yend) into ring blocks base + 1 ..
+        // base + M, and H of the rows evaluated this step, [s - R, s - R +
+        // CH), into Hr; columns [xa, xend).  (An evaluated row y < yb has
+        // y + R = s + i < yend, so its item is never skipped.)
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int i = it_row[k], x0 = it_x0[k];
@@ -185,8 +188,7 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
                 int blk = base + 1 + i / R;
                 blk = blk >= NRB ? blk - NRB : blk;
                 const int ro = (blk * R + i % R) * PITCH - ox;
-                float *qrow = Qr + ro, *hrow = Hr + ro;
-                // H of rows in [yb, yend) is never read; writing it is harmless
+                float *qrow = Qr + ro, *hrow = Hr + i * PITCH - ox;
                 constexpr bool HF = MODE != MODE_FAST;  // the fast mode needs no H
                 float q = v[0], h = p[0];
 #pragma unroll
@@ -231,17 +233,18 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
                 const int bd = bu + 1 >= NRB ? bu + 1 - NRB : bu + 1;
                 const int ou = (bu * R + i % R) * PITCH + lx;
                 const int od = (bd * R + i % R) * PITCH + lx;
+                const int oh = i * PITCH + lx;
                 const float c = pr[i];
                 const float nw = Qr[ou], ne = Qr[ou + R], sw = Qr[od], se = Qr[od + R];
                 if constexpr (MODE == MODE_BOX) {
-                    out_v[i] = S::round(box_sum(nw, ne, sw, se, Hr[ou], Hr[ou + R], vr[i], vr[i + R], c) * inv_box);
+                    out_v[i] = S::round(box_sum(nw, ne, sw, se, Hr[oh], Hr[oh + R], vr[i], vr[i + R], c) * inv_box);
                     out_i[i] = 0;
                 } else {
                     float d[8];
                     if constexpr (MODE == MODE_FAST)
                         fast_distances(d, nw, ne, sw, se, c, fr1);
                     else
-                        exact_distances(d, nw, ne, sw, se, Hr[ou], Hr[ou + R], vr[i], vr[i + R], c, fr1, f2r1, N);
+                        exact_distances(d, nw, ne, sw, se, Hr[oh], Hr[oh + R], vr[i], vr[i + R], c, fr1, f2r1, N);
                     const Pick pk = select8<SEL>(d);
                     out_v[i] = S::round(fmaf(pk.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c));
                     out_i[i] = pk.idx;
