@@ -73,14 +73,15 @@ const int kRegions[][2] = {{64, 64}, {128, 64}, {64, 128}, {96, 96}, {128, 128},
 
 Plan make_plan(int geom, int RW, int RH, int r, int k) {
     Plan p;
-    if (stream_geom(geom)) {  // one sweep per launch; strips of whole blocks of r columns
-        const int tw = ((RW - 2 * r) / r) * r;
-        if (k != 1 || !fixed_radius(r) || tw < std::max(r, 4)) return Plan{};
+    if (stream_geom(geom)) {  // one or two sweeps per launch; strips of whole blocks of r columns
+        if (!fixed_radius(r) || k > 2 || (k == 2 && !stream_fusable(RW, r))) return Plan{};
+        const int tw = ((RW - 2 * k * r) / r) * r;
+        if (tw < std::max(r, 4)) return Plan{};
         p.geom = geom;
         p.tw = tw;
         p.th = 0;  // rows per workgroup chosen at launch to fill the device once
-        p.k = 1;
-        p.lds = stream_lds_bytes(RW, r);
+        p.k = k;
+        p.lds = k == 2 ? stream2_lds_bytes(RW, r) : stream_lds_bytes(RW, r);
         return p;
     }
     if (!fwd_tile_shape(RW, RH, r, k, &p.tw, &p.th)) return Plan{};
@@ -100,7 +101,7 @@ Plan make_plan(int geom, int RW, int RH, int r, int k) {
 // load, HBM traffic that shrinks as 1/k, and a penalty for low occupancy.
 double plan_cost(const Plan &p, int H, int W, int r) {
     if (stream_geom(p.geom))  // selection on tw of RW columns, no vertical halo to speak of
-        return 0.75 * kGeomDims[p.geom][0] / std::min(p.tw, W) + 0.25;
+        return 0.75 * kGeomDims[p.geom][0] / std::min(p.tw, W) + 0.25 / p.k;
     const double tw = std::min(p.tw, W), th = std::min(p.th, H);
     double work = 0;
     for (int j = 0; j < p.k; ++j) {
@@ -124,13 +125,12 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 // Measured defaults for the compiled radii (3x2048x2048 FP32, T=30 on
 // MI355X, plan sweep over geometries, fusion depths, streaming strip widths
 // and rows per workgroup, 0 = chosen to fill the device once), in order of
-// preference: the
-// row-streaming kernel from r=2 up, the tiled kernel with three fused sweeps
-// at r=1 (the later entries are fallbacks for devices whose LDS does not fit
+// preference: the row-streaming kernel, with two fused sweeps per launch at
+// r <= 2 (the later entries are fallbacks for devices whose LDS does not fit
 // the first).
 struct TunedShape { int r, geom, k, rows; };
-const TunedShape kTuned[] = {{1, GEOM_64x48, 3, 0},
-                             {2, GEOM_S256, 1, 0}, {2, GEOM_64x48, 2, 0},
+const TunedShape kTuned[] = {{1, GEOM_S128, 2, 0}, {1, GEOM_64x48, 3, 0},
+                             {2, GEOM_S128, 2, 0}, {2, GEOM_64x48, 2, 0},
                              {3, GEOM_S128, 1, 0}, {3, GEOM_64x48, 2, 0},
                              {4, GEOM_S192, 1, 32}, {4, GEOM_64x48, 1, 0},
                              {5, GEOM_S128, 1, 0}, {5, GEOM_64x60, 1, 0},

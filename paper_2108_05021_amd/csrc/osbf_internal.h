@@ -33,10 +33,13 @@ inline bool stream_geom(int g) { return g == GEOM_S128 || g == GEOM_S256 || g ==
 bool fwd_tile_shape(int RW, int RH, int r, int k, int *tw, int *th);
 void fwd_lds_layout(int tw, int th, int r, int k, int *pitch, int *arr);
 hipError_t launch_forward(int dtype, const FwdLaunch &a, hipStream_t s);
-// Row-streaming kernel (k = 1, any mode): strips of tw columns, chunks of th
+// Row-streaming kernel (k = 1, or 2 fused sweeps at small r; any mode):
+// strips of tw columns, chunks of th
 // rows (th = 0: the launch chooses th so that the chunks fill the device's
 // resident workgroup slots once).
 int stream_step(int r);                       // rows per step (th is a multiple)
+size_t stream2_lds_bytes(int RW, int r);      // the fused two-sweep kernel (k = 2)
+bool stream_fusable(int RW, int r);           // whether that kernel exists for (RW, r)
 size_t stream_lds_bytes(int RW, int r);
 hipError_t launch_forward_stream(int dtype, const FwdLaunch &a, hipStream_t s);
 hipError_t launch_forward_stream_mode(int mode, int dtype, const FwdLaunch &a, hipStream_t s);

@@ -10,6 +10,15 @@ size_t stream_lds_bytes(int RW, int r) {
     return (size_t)(4 * ch + r) * (RW + 1) * sizeof(float);
 }
 
+// The fused two-sweep kernel: P, V and H staging (CH rows each) and one Q
+// ring (CH + r rows) per sweep.
+size_t stream2_lds_bytes(int RW, int r) {
+    const int ch = stream_step_rows(r);
+    return (size_t)(5 * ch + 2 * r) * (RW + 1) * sizeof(float);
+}
+
+bool stream_fusable(int RW, int r) { return stream2_radius(r) && RW >= 5 * r; }
+
 int stream_step(int r) { return stream_step_rows(r); }
 
 hipError_t launch_forward_stream(int dtype, const FwdLaunch &a, hipStream_t s) {

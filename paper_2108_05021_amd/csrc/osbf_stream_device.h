@@ -271,6 +271,284 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
     if (pending && own) store_step();
 }
 
+// Two fused sweeps on one work item (small radii): stage A runs the first
+// sweep on the strip grown by R on each side (rows grown by R), reading the
+// input from global memory; its rounded results, still in the lane's
+// registers, are stage B's new input rows, from which stage B runs the
+// second sweep on the strip itself.  Rows stage B needs above row 0 or below
+// row H-1 are replicated from those rows (the clamp), so stage B sees
+// exactly the clamp extension of the first sweep's output.  The P and V
+// staging and the H rows are shared (stage B's phases follow stage A's after
+// barriers), each stage keeps its own Q ring: LDS (5 CH + 2R) rows, four
+// barriers per step of CH rows of both sweeps.  The region is TW + 4R
+// columns wide.  Every block and column anchor is a multiple of R, so the
+// results are those of two single-sweep launches, bit for bit.
+template <int DT, int R, int RW, int CH, bool SEL, int MODE>
+__device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, float *lds) {
+    using S = Storage<DT>;
+    using T = typename S::T;
+    static_assert(CH % R == 0, "a step is whole blocks of R rows");
+    static_assert(RW % 64 == 0 && RW >= 5 * R, "region width");
+    constexpr int M = CH / R, NRB = M + 1, PITCH = RW + 1;
+    float *const Pl = lds;                          // CH rows
+    float *const Vl = lds + CH * PITCH;             // CH rows
+    float *const Hr = lds + 2 * CH * PITCH;         // CH rows
+    float *const QA = lds + 3 * CH * PITCH;         // NRB * R rows (stage A ring)
+    float *const QB = QA + NRB * R * PITCH;         // NRB * R rows (stage B ring)
+
+    const int lx = threadIdx.x;
+    const int H = a.H, W = a.W, TW = a.tw, YC = a.th;
+    const int ntiles = a.tiles_x * a.tiles_y;
+    const int plane = t / ntiles, tile = t - plane * ntiles;
+    const int chunk = tile / a.tiles_x, strip = tile - chunk * a.tiles_x;
+    const int X0 = strip * TW, Y0 = chunk * YC;
+    const int yb = min(H, Y0 + YC);
+    const int ox = X0 - 2 * R;  // image column of region column 0
+    const int x = ox + lx;
+    const size_t plane_off = (size_t)plane * H * W;
+    const T *src = (const T *)a.src + plane_off + min(max(x, 0), W - 1);
+    T *dst = (T *)a.dst + plane_off;
+    uint8_t *selA = SEL ? a.sel + plane_off : nullptr;
+    uint8_t *selB = SEL ? a.sel + a.sel_stride + plane_off : nullptr;
+
+    // stage geometry: evaluated columns [xa, xb) and rows [ya, ye), fields
+    // on columns [xa, xend) and rows up to yend, row sums reading [lo, hi]
+    struct Geo { int xa, xb, xend, lo, hi, ya, ye, yend, nb; };
+    auto geo = [&](int xa, int xb, int ya, int ye) {
+        Geo g;
+        g.xa = xa; g.xb = xb; g.xend = xb + R;
+        g.lo = max(0, xa - R); g.hi = min(W, g.xend) - 1;
+        g.ya = ya; g.ye = ye; g.yend = ye + R;
+        g.nb = (g.xend - xa + R - 1) / R;
+        return g;
+    };
+    const Geo gA = geo(max(0, X0 - R), min(W, X0 + TW + R), max(0, Y0 - R), min(H, yb + R));
+    const Geo gB = geo(X0, min(W, X0 + TW), Y0, yb);
+    const bool ownA = x >= gA.xa && x < gA.xb, ownB = x >= gB.xa && x < gB.xb;
+    const bool coreA = x >= X0 && x < X0 + TW;  // stage A writes maps only here
+
+    // each stage's row-sum items, the same every step (as fwd_stream_item)
+    struct Items { int row[M], x0[M]; bool ok[M], fast[M]; };
+    auto items = [&](const Geo &g) {
+        Items it;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int i = lx + k * RW;
+            const int m = i / (R * g.nb), rem = i - m * (R * g.nb);
+            const int b = rem / R;
+            it.ok[k] = i < CH * g.nb;
+            it.row[k] = m * R + (rem - b * R);
+            it.x0[k] = g.xa + b * R;
+            it.fast[k] = it.x0[k] - R >= g.lo && it.x0[k] + R - 1 <= g.hi;
+        }
+        return it;
+    };
+    const Items iA = items(gA), iB = items(gB);
+
+    constexpr float fr1 = (float)(R + 1), f2r1 = (float)(2 * R + 1);
+    constexpr float N = fr1 * fr1 * f2r1;
+    const float invN = 1.0f / N;
+    const float inv_box = 1.0f / (f2r1 * f2r1);
+
+    float prA[CH + R], vrA[CH + R], prB[CH + R], vrB[CH + R];
+    float outA[CH], outB[CH];
+    int idxA[CH], idxB[CH];
+    T raw[CH];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        prA[i] = S::cvt(src[(size_t)min(max(gA.ya - R + i, 0), H - 1) * W]);
+        vrA[i] = prB[i] = vrB[i] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < CH; ++i) outA[i] = outB[i] = 0.f;
+    auto load_step = [&](int s0) {
+#pragma unroll
+        for (int i = 0; i < CH; ++i) raw[i] = src[(size_t)min(max(s0 + i, 0), H - 1) * W];
+    };
+
+    // V of the step's new rows in registers; P of the rows evaluated this step
+    // and the new V rows to LDS
+    auto v_phase = [&](float *pr, float *vr) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float *p = pr + m * R;
+            float v = p[0];
+#pragma unroll
+            for (int tt = 1; tt <= R; ++tt) v += p[tt];
+            vr[R + m * R] = v;
+#pragma unroll
+            for (int tt = 1; tt < R; ++tt) {
+                v += p[R + tt] - p[tt - 1];
+                vr[R + m * R + tt] = v;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            Pl[i * PITCH + lx] = pr[i];
+            Vl[i * PITCH + lx] = vr[R + i];
+        }
+    };
+    // Q of rows [s, s + CH) into the ring, H of rows [s - R, s - R + CH)
+    auto qh_phase = [&](const Geo &g, const Items &it, int s0, int base, float *Q) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int i = it.row[k], x0 = it.x0[k];
+            if (!it.ok[k] || s0 + i >= g.yend) continue;
+            const float *vrow = Vl + i * PITCH - ox;  // + image column
+            const float *prow = Pl + i * PITCH - ox;
+            float v[2 * R], p[2 * R];
+            if (it.fast[k]) {
+#pragma unroll
+                for (int tt = 0; tt < 2 * R; ++tt) {
+                    v[tt] = vrow[x0 - R + tt];
+                    p[tt] = prow[x0 - R + tt];
+                }
+            } else {
+#pragma unroll
+                for (int tt = 0; tt < 2 * R; ++tt) {
+                    const int col = min(max(x0 - R + tt, g.lo), g.hi);
+                    v[tt] = vrow[col];
+                    p[tt] = prow[col];
+                }
+            }
+            int blk = base + 1 + i / R;
+            blk = blk >= NRB ? blk - NRB : blk;
+            float *qrow = Q + (blk * R + i % R) * PITCH - ox, *hrow = Hr + i * PITCH - ox;
+            constexpr bool HF = MODE != MODE_FAST;
+            float q = v[0], h = p[0];
+#pragma unroll
+            for (int tt = 1; tt <= R; ++tt) {
+                q += v[tt];
+                if (HF) h += p[tt];
+            }
+            qrow[x0] = q;
+            if (HF) hrow[x0] = h;
+#pragma unroll
+            for (int tt = 1; tt < R; ++tt) {
+                if (x0 + tt < g.xend) {
+                    q += v[R + tt] - v[tt - 1];
+                    qrow[x0 + tt] = q;
+                    if (HF) {
+                        h += p[R + tt] - p[tt - 1];
+                        hrow[x0 + tt] = h;
+                    }
+                }
+            }
+        }
+    };
+    // rows [s - R, s - R + CH) ∩ [ya, ye) of this lane's column
+    auto eval_phase = [&](const Geo &g, int s0, int base, const float *Q, const float *pr, const float *vr,
+                          float *out, int *idx) {
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int y = s0 - R + i;
+            if (y < g.ya || y >= g.ye) continue;  // uniform over the workgroup
+            int bu = base + i / R;
+            bu = bu >= NRB ? bu - NRB : bu;
+            const int bd = bu + 1 >= NRB ? bu + 1 - NRB : bu + 1;
+            const int ou = (bu * R + i % R) * PITCH + lx;
+            const int od = (bd * R + i % R) * PITCH + lx;
+            const int oh = i * PITCH + lx;
+            const float c = pr[i];
+            const float nw = Q[ou], ne = Q[ou + R], sw = Q[od], se = Q[od + R];
+            if constexpr (MODE == MODE_BOX) {
+                out[i] = S::round(box_sum(nw, ne, sw, se, Hr[oh], Hr[oh + R], vr[i], vr[i + R], c) * inv_box);
+                idx[i] = 0;
+            } else {
+                float d[8];
+                if constexpr (MODE == MODE_FAST)
+                    fast_distances(d, nw, ne, sw, se, c, fr1);
+                else
+                    exact_distances(d, nw, ne, sw, se, Hr[oh], Hr[oh + R], vr[i], vr[i + R], c, fr1, f2r1, N);
+                const Pick pk = select8<SEL>(d);
+                out[i] = S::round(fmaf(pk.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c));
+                idx[i] = pk.idx;
+            }
+        }
+    };
+
+    const int nsteps = (yb + 2 * R - gA.ya + CH - 1) / CH;
+    int baseA = 0, baseB = 0, outB_s = 0;
+    bool pending = false;
+    auto store_B = [&]() {
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int y = outB_s - R + i;
+            if (y >= Y0 && y < yb) {
+                const size_t o = (size_t)y * W + x;
+                dst[o] = S::pack(outB[i]);
+                if (SEL) selB[o] = (uint8_t)idxB[i];
+            }
+        }
+    };
+    load_step(gA.ya);
+    for (int n = 0; n < nsteps; ++n) {
+        const int sA = gA.ya + n * CH, sB = sA - R;
+        // stage A: the first sweep from the input
+#pragma unroll
+        for (int i = 0; i < CH; ++i) prA[R + i] = S::cvt(raw[i]);
+        v_phase(prA, vrA);
+        if (pending && ownB) store_B();
+        if (n + 1 < nsteps) load_step(sA + CH);
+        __syncthreads();
+        qh_phase(gA, iA, sA, baseA, QA);
+        __syncthreads();
+        if (ownA) {
+            eval_phase(gA, sA, baseA, QA, prA, vrA, outA, idxA);
+            if (SEL && coreA) {
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const int y = sA - R + i;
+                    if (y >= Y0 && y < yb) selA[(size_t)y * W + x] = (uint8_t)idxA[i];
+                }
+            }
+        }
+        // stage B: its new rows [sB, sB + CH) are stage A's rows just
+        // evaluated; rows outside the image repeat row 0 or row H - 1
+#pragma unroll
+        for (int i = 0; i < CH; ++i) prB[R + i] = outA[i];
+        {
+            const int j0 = R - sB, jH = H - 1 + R - sB;  // window indices of rows 0 and H - 1
+            if (j0 > 0 && j0 < R + CH) {  // uniform
+                const float v0 = prB[0];
+                float top = v0;
+#pragma unroll
+                for (int j = 0; j < R + CH; ++j)
+                    if (j == j0) top = prB[j];
+#pragma unroll
+                for (int j = 0; j < R + CH; ++j)
+                    if (j < j0) prB[j] = top;
+            }
+            if (jH >= 0 && jH < R + CH - 1) {  // uniform
+                float bot = prB[0];
+#pragma unroll
+                for (int j = 0; j < R + CH; ++j)
+                    if (j == jH) bot = prB[j];
+#pragma unroll
+                for (int j = 0; j < R + CH; ++j)
+                    if (j > jH) prB[j] = bot;
+            }
+        }
+        v_phase(prB, vrB);
+        __syncthreads();
+        qh_phase(gB, iB, sB, baseB, QB);
+        __syncthreads();
+        if (ownB) eval_phase(gB, sB, baseB, QB, prB, vrB, outB, idxB);
+        outB_s = sB;
+        pending = true;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            prA[i] = prA[CH + i];
+            vrA[i] = vrA[CH + i];
+            prB[i] = prB[CH + i];
+            vrB[i] = vrB[CH + i];
+        }
+        baseA = baseA == 0 ? M : baseA - 1;
+        baseB = baseB == 0 ? M : baseB - 1;
+    }
+    if (pending && ownB) store_B();
+}
+
 // Waves per SIMD the register allocation must leave room for (the LDS ring
 // allows about this many workgroups per CU at the default strip widths).
 constexpr int stream_min_waves(int r) { return r >= 16 ? 2 : r >= 10 ? 3 : 4; }
@@ -282,11 +560,28 @@ void fwd_stream_kernel(FwdLaunch a) {
     fwd_stream_item<DT, R, RW, CH, SEL, MODE>(a, xcd_remap(blockIdx.x, a.tiles_x * a.tiles_y * a.planes), lds);
 }
 
+// Radii with a fused two-sweep streaming kernel (halo 2r per side).
+constexpr bool stream2_radius(int r) { return r <= 5; }
+
+template <int DT, int R, int RW, int CH, bool SEL, int MODE = MODE_EXACT>
+__global__ __launch_bounds__(RW) __attribute__((amdgpu_waves_per_eu(stream_min_waves(R))))
+void fwd_stream2_kernel(FwdLaunch a) {
+    extern __shared__ float lds[];
+    fwd_stream2_item<DT, R, RW, CH, SEL, MODE>(a, xcd_remap(blockIdx.x, a.tiles_x * a.tiles_y * a.planes), lds);
+}
+
 template <int DT, int R, int RW, bool SEL, int MODE>
 hipError_t launch_stream(const FwdLaunch &a, hipStream_t stream) {
     constexpr int CH = stream_step_rows(R);
-    const size_t lds = stream_lds_bytes(RW, R);
-    auto kern = fwd_stream_kernel<DT, R, RW, CH, SEL, MODE>;
+    const bool fused = a.k == 2;
+    if constexpr (!stream2_radius(R) || RW < 5 * R) {
+        if (fused) return hipErrorInvalidValue;
+    }
+    const size_t lds = fused ? stream2_lds_bytes(RW, R) : stream_lds_bytes(RW, R);
+    const void *kern = (const void *)fwd_stream_kernel<DT, R, RW, CH, SEL, MODE>;
+    if constexpr (stream2_radius(R) && RW >= 5 * R) {
+        if (fused) kern = (const void *)fwd_stream2_kernel<DT, R, RW, CH, SEL, MODE>;
+    }
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -295,18 +590,18 @@ hipError_t launch_stream(const FwdLaunch &a, hipStream_t stream) {
     if (a.th <= 0) {
         // rows per workgroup chosen so that the strips' chunks fill the
         // device's resident workgroup slots once (no partial last wave)
-        static std::atomic<int> slots[64];  // per device; 0 = not yet queried
+        static std::atomic<int> slots[2][64];  // per kernel and device; 0 = not yet queried
         int dev = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
-        int n = dev < 64 ? slots[dev].load(std::memory_order_relaxed) : 0;
+        int n = dev < 64 ? slots[fused][dev].load(std::memory_order_relaxed) : 0;
         if (!n) {
             int cus = 0, per_cu = 0;
             e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, RW, lds);
             if (e != hipSuccess) return e;
             n = std::max(1, cus * per_cu);
-            if (dev < 64) slots[dev].store(n, std::memory_order_relaxed);
+            if (dev < 64) slots[fused][dev].store(n, std::memory_order_relaxed);
         }
         const long long strips = (long long)a.tiles_x * a.planes;
         const int per_strip = (int)std::max<long long>(1, n / strips);
@@ -316,7 +611,9 @@ hipError_t launch_stream(const FwdLaunch &a, hipStream_t stream) {
         b.tiles_y = (a.H + rows - 1) / rows;
     }
     const int blocks = b.tiles_x * b.tiles_y * b.planes;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(RW), lds, stream, b);
+    void *args[] = {(void *)&b};
+    hipError_t e = hipLaunchKernel(kern, dim3(blocks), dim3(RW), args, lds, stream);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -332,7 +629,7 @@ hipError_t launch_stream_w(const FwdLaunch &a, hipStream_t s) {
 
 template <int DT, bool SEL, int MODE>
 hipError_t launch_stream_r(const FwdLaunch &a, hipStream_t s) {
-    if (a.k != 1 || !stream_geom(a.geom)) return hipErrorInvalidValue;
+    if (a.k < 1 || a.k > 2 || !stream_geom(a.geom)) return hipErrorInvalidValue;
     switch (a.r) {
     case 1: return launch_stream_w<DT, 1, SEL, MODE>(a, s);
     case 2: return launch_stream_w<DT, 2, SEL, MODE>(a, s);

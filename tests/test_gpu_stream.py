@@ -104,3 +104,65 @@ def test_stream_modes_equal_tiled(dev, r):
         with plan(geom, 1):
             assert torch.equal(osbf.forward_fast(x, r, 3), f)
             assert torch.equal(osbf.box_forward(x, r, 3), b)
+
+
+@pytest.mark.parametrize("geom", [5, 6, 7])
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5])
+def test_fused_two_sweeps_equal_single_sweeps(dev, geom, r):
+    """Two sweeps fused in one streaming launch (k = 2; odd T adds a
+    single-sweep launch) give the bits and both sweeps' maps of single-sweep
+    launches, on ragged shapes, several row chunkings, and image edges that
+    the clamp replicates between the sweeps."""
+    rng = np.random.default_rng(1000 + 10 * r + geom)
+    for shape in [(2, 97, 301), (1, 260, 70), (1, 3, 500), (1, 500, 3), (1, 1, 1), (1, 2, 2)]:
+        img = synth.voronoi(shape[1], shape[2], 9, 0.05, rng, C=shape[0])
+        x = torch.from_numpy(img).to(dev)
+        for T in (2, 3, 5):
+            with plan(1, 1):
+                want, wsel = osbf.forward(x, r, T, return_sel=True)
+            for rows in (0, STEP[r], 3 * STEP[r] + 1):
+                with plan(geom, 2, rows):
+                    tw, th, k, launches = _plan_shape(*shape, r, T)
+                    assert k == 2 and launches == (T + 1) // 2
+                    y, sel = osbf.forward(x, r, T, return_sel=True)
+                    y2 = osbf.forward(x, r, T)
+                assert torch.equal(y, want) and torch.equal(sel, wsel), (shape, T, rows)
+                assert torch.equal(y2, want), (shape, T, rows)
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("r", [1, 2, 5])
+def test_fused_two_sweeps_reduced_precision(dev, dtype, r):
+    """F16/BF16: the first sweep's result is rounded to the storage type
+    before the second sweep reads it, in registers as in LDS."""
+    rng = np.random.default_rng(1100 + r)
+    x = torch.from_numpy(synth.voronoi(210, 333, 11, 0.03, rng, C=2)).to(dev).to(dtype)
+    with plan(1, 1):
+        want = osbf.forward(x, r, 4)
+    for geom in (5, 6):
+        with plan(geom, 2):
+            assert torch.equal(osbf.forward(x, r, 4), want)
+
+
+@pytest.mark.parametrize("r", [1, 2, 5])
+def test_fused_two_sweeps_modes(dev, r):
+    rng = np.random.default_rng(1200 + r)
+    x = torch.from_numpy(synth.voronoi(170, 290, 7, 0.05, rng, C=2)).to(dev)
+    with plan(1, 1):
+        f = osbf.forward_fast(x, r, 4)
+        b = osbf.box_forward(x, r, 4)
+    with plan(6, 2):
+        assert torch.equal(osbf.forward_fast(x, r, 4), f)
+        assert torch.equal(osbf.box_forward(x, r, 4), b)
+
+
+def test_fused_full_size(dev):
+    """3x2048x2048 (the benchmark image), r=2 and 5, T=4: fused streaming
+    plans equal single-sweep launches."""
+    x = torch.from_numpy(synth.workload_rgb()).to(dev)
+    for r in (2, 5):
+        with plan(1, 1):
+            want = osbf.forward(x, r, 4)
+        for geom in (5, 6, 7):
+            with plan(geom, 2):
+                assert torch.equal(osbf.forward(x, r, 4), want), (r, geom)
