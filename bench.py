@@ -54,8 +54,15 @@ C = 3
 # checked separately through the plans)
 FWD_KERNEL_SOURCES = ("osbf_device.h", "osbf_fwd_device.h", "osbf_forward.hip", "osbf_stream_device.h",
                       "osbf_stream.hip")
-# the kernel the bench plans launch for r in RADII (the row-streaming kernel)
-FWD_KERNEL_NAME = "osbf::fwd_stream_kernel"
+
+
+def fwd_kernel_name(plan) -> str:
+    """The forward kernel a plan launches: the row-streaming kernels have a
+    tile height of 0 (rows chosen at launch), the fused two-sweep one for
+    plans that fuse two sweeps."""
+    if plan["tile"][1] == 0:
+        return "osbf::fwd_stream2_kernel" if plan["fused"] == 2 else "osbf::fwd_stream_kernel"
+    return "osbf::fwd_fixed_kernel"
 
 
 def kernel_source_hash() -> str:
@@ -381,7 +388,8 @@ def main():
         p = plans[r]
         launch_us = per_r_ms[r] * 1e3 / p["launches"]
         alg_bytes = BYTES_PER_PX_SWEEP * C * H * W * p["fused"]
-        kernels.append({"r": r, "tile": list(p["tile"]), "fused": p["fused"], "launches": p["launches"],
+        kernels.append({"r": r, "kernel": fwd_kernel_name(p), "tile": list(p["tile"]), "fused": p["fused"],
+                        "launches": p["launches"],
                         "avg_launch_us": round(launch_us, 2),
                         "achieved_GBs": round(alg_bytes / launch_us / 1e3, 1),
                         "mpix_it_s": round(C * H * W * T_SWEEPS / (per_r_ms[r] / 1e3) / 1e6, 1)})
@@ -408,7 +416,7 @@ def main():
                    "planes": C, "height": H, "width": W, "radii": list(RADII), "iterations": T_SWEEPS},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": FWD_KERNEL_NAME, "kernels": kernels,
+                     "kernel": " + ".join(dict.fromkeys(k["kernel"] for k in kernels)), "kernels": kernels,
                      "bytes_per_px_sweep": BYTES_PER_PX_SWEEP},
     }
     if not args.no_cpu_baseline:

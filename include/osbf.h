@@ -320,7 +320,10 @@ size_t osbf_gaussian_workspace_size(int32_t planes, int32_t height, int32_t widt
  *   ws         device workspace of osbf_gaussian_workspace_size bytes (one
  *              FP32 plane set; needed when iterations >= 2 or in place)
  * Replicate boundary at every sweep; stream-ordered and asynchronous;
- * arguments are checked before any launch.  FP32 arithmetic.
+ * arguments are checked before any launch.  FP32 arithmetic.  Two kernels
+ * with bit-identical results: row streaming (default) and 64 x 64 tiles;
+ * OSBF_GAUSS=tiled or OSBF_GAUSS=stream[,lanes[,rows]] in the environment
+ * selects one (tests, sweeps).
  */
 osbf_status osbf_gaussian_forward(const float *src, float *dst, int32_t planes, int32_t height,
                                   int32_t width, int32_t radius, float sigma, int32_t iterations,

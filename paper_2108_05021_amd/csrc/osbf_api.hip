@@ -870,11 +870,7 @@ osbf_status osbf_gaussian_forward(const float *src, float *dst, int32_t planes, 
 
     GaussLaunch a;
     a.planes = planes; a.H = H; a.W = W; a.r = r;
-    gauss_tile(r, &a.tw, &a.th);
-    a.tiles_x = (W + a.tw - 1) / a.tw;
-    a.tiles_y = (H + a.th - 1) / a.th;
-    if ((long long)a.tiles_x * a.tiles_y * planes >= (1LL << 31))
-        return fail(OSBF_ERROR_INVALID_VALUE, "too many tiles");
+    if (!gauss_geometry(a)) return fail(OSBF_ERROR_INVALID_VALUE, "too many tiles");
     // taps g(u) = exp(-u^2 / (2 sigma^2)) (1 for sigma = infinity); the
     // normalisers come from the FP32 taps the kernel uses
     double zh = 0.0;

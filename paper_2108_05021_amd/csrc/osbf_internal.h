@@ -98,11 +98,15 @@ struct GaussLaunch {
     uint8_t *sel;         // nullable [planes][H][W] map of this sweep
     int planes, H, W, r;
     int tw, th, tiles_x, tiles_y;
+    int lanes;            // streaming kernel's strip lanes (tw = lanes - 2r, th = 0: rows
+                          // chosen at launch); 0 = tiled kernel
     float g[OSBF_GAUSS_MAX_R + 1];  // taps g(0..r), g(0) = 1
     float w_q, w_h, N, invN;        // distance weights: Zf, Zh, Zh^2 Zf, 1/N
 };
 bool gauss_radius(int r);
 void gauss_tile(int r, int *tw, int *th);
+// Kernel and tiling for a.r, a.H, a.W, a.planes (false if the grid is too large).
+bool gauss_geometry(GaussLaunch &a);
 hipError_t launch_gauss(const GaussLaunch &a, hipStream_t s);
 
 }  // namespace osbf

@@ -115,3 +115,37 @@ def test_full_size_crops(dev):
         assert gap.max() <= _tau(r, sigma, sub)
         want = np.take_along_axis(means[core], s[..., None], 2)[..., 0]
         assert np.abs(y[p, y0:y0 + n, x0:x0 + n].cpu().numpy() - want).max() <= 1e-5
+
+
+@pytest.mark.parametrize("r,sigma", [(1, 0.7), (2, 1.0), (3, 1.5), (4, 2.0), (5, 2.5), (6, 10.0), (7, 3.0), (8, 4.0)])
+def test_stream_equals_tiled(dev, monkeypatch, r, sigma):
+    """The row-streaming kernel adds every tap in the tiled kernel's order:
+    values and maps agree bit for bit, for both strip widths, rows per
+    workgroup chosen at launch or fixed (several steps and a ragged last
+    step), images narrower than a strip, one row or one column."""
+    rng = np.random.default_rng(500 + r)
+    for shape in [(2, 67, 131), (1, 150, 300), (3, 33, 45), (1, 1, 90), (1, 90, 1), (1, 203, 517)]:
+        img = synth.voronoi(shape[1], shape[2], 7, 0.05, rng, C=shape[0])
+        x = torch.from_numpy(img).to(dev)
+        monkeypatch.setenv("OSBF_GAUSS", "tiled")
+        want, want_sel = osbf.gaussian_forward(x, r, sigma, 2, return_sel=True)
+        for mode in ("stream", "stream,128,0", "stream,256,0", "stream,128,16", "stream,256,40", "stream,128,1"):
+            monkeypatch.setenv("OSBF_GAUSS", mode)
+            got, got_sel = osbf.gaussian_forward(x, r, sigma, 2, return_sel=True)
+            assert torch.equal(got_sel, want_sel), (shape, mode)
+            assert torch.equal(got, want), (shape, mode)
+            assert torch.equal(osbf.gaussian_forward(x, r, sigma, 2), want), (shape, mode)
+
+
+def test_stream_equals_tiled_full_size(dev, monkeypatch):
+    """3x2048x2048 (the benchmark image), r = 2, 5, 8, two sweeps: the
+    streaming kernel's launch-chosen rows per workgroup against the tiled
+    kernel, bit for bit."""
+    x = torch.from_numpy(synth.workload_rgb()).to(dev)
+    for r in (2, 5, 8):
+        monkeypatch.setenv("OSBF_GAUSS", "tiled")
+        want, want_sel = osbf.gaussian_forward(x, r, r / 2.0, 2, return_sel=True)
+        monkeypatch.delenv("OSBF_GAUSS")
+        got, got_sel = osbf.gaussian_forward(x, r, r / 2.0, 2, return_sel=True)
+        assert torch.equal(got_sel, want_sel), r
+        assert torch.equal(got, want), r
