@@ -23,6 +23,9 @@ plain FP32 forward on the same workload:
             r in {2,5,8} with sigma = r/2, T=10, next to the box filter
   autotune  the bench workload with the plans osbf_autotune measures on this
             device, next to the measured table the timed step uses
+  small     one 256x256 plane (12 rectangles, sigma 0.05), r=2, T=10: launch
+            bound, so reported as microseconds per call, eager and replayed
+            from a HIP graph, with the table plan and the autotuned one
 
 Prints one JSON line (see the repository's benchmark contract).  Inputs are
 resident in HBM before every timed region; each timed region is bracketed by
@@ -263,6 +266,52 @@ def form_gaussian(reps):
     return res
 
 
+def form_small(reps):
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    x = torch.from_numpy(synth.workload_single()).cuda()
+    planes, H, W = x.shape
+    r, T = 2, 10
+    out = torch.empty_like(x)
+    ws = torch.empty(max(1, osbf.forward_workspace_size(planes, H, W, torch.float32, r, T)),
+                     dtype=torch.uint8, device=x.device)
+    res = {"workload": "1x256x256 f32, 12 rectangles on 0.5 + N(0,0.05^2), r=2, T=10, replicate boundary"}
+    n = 40 * reps
+
+    def measure(tag):
+        def call():
+            osbf.osbf_forward(x, out, r, T, ws=ws)
+        call()
+        torch.cuda.synchronize()
+        want = out.clone()
+        t_eager = _timed(call, n, warmup=20)
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(g, stream=st):
+                call()
+        torch.cuda.current_stream().wait_stream(st)
+        for _ in range(3):  # every replay equals the eager result
+            out.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            if not torch.equal(out, want):
+                raise RuntimeError("graph replay differs from the eager forward")
+        t_graph = _timed(g.replay, n, warmup=20)
+        plan = osbf.forward_plan(planes, H, W, torch.float32, r, T)
+        res[tag] = {"plan": {"tile": list(plan["tile"]), "fused": plan["fused"], "launches": plan["launches"]},
+                    "eager_us": round(t_eager * 1e6, 2), "graph_us": round(t_graph * 1e6, 2),
+                    "eager_mpix_it_s": round(x.numel() * T / t_eager / 1e6, 1),
+                    "graph_mpix_it_s": round(x.numel() * T / t_graph / 1e6, 1)}
+
+    measure("table")
+    osbf.autotune(x, r, T)
+    measure("autotuned")
+    osbf.autotune_clear()
+    return res
+
+
 def form_autotune(reps):
     import torch
     from paper_2108_05021_amd import osbf, synth
@@ -316,6 +365,15 @@ def form_variants(reps):
             "paper_context": "fast/exact ~0.6 and exact/box ~8 (MATLAB) or ~6 (C++) on a laptop CPU, r unstated"}
 
 
+FORMS = ("batched", "precision", "fwd_bwd", "variants", "volume", "gaussian", "small", "autotune")
+
+
+def run_form(name, args, reps=5):
+    if name == "precision":
+        return form_precision(reps, errors=not args.no_errors)
+    return globals()["form_" + name](reps)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +382,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched/bf16/f16/fwd+bwd forms")
     ap.add_argument("--no-errors", action="store_true", help="skip the oracle error crops of the bf16/f16 form")
+    ap.add_argument("--form", choices=sorted(FORMS), default=None,
+                    help="run only this form (for profiling it) and print its result; no timed step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (for scaling HBM counters)")
     args = ap.parse_args()
@@ -340,6 +400,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the filter's multi-GPU "
               "sharding is a design note, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.form:
+        print(json.dumps({"form": args.form, **run_form(args.form, args)}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -424,14 +487,7 @@ def main():
     if not args.no_forms:
         del x, out, ws
         torch.cuda.empty_cache()
-        reps = 5
-        line["forms"] = {"batched": form_batched(reps),
-                         "precision": form_precision(reps, errors=not args.no_errors),
-                         "fwd_bwd": form_fwd_bwd(reps),
-                         "variants": form_variants(reps),
-                         "volume": form_volume(reps),
-                         "gaussian": form_gaussian(reps),
-                         "autotune": form_autotune(reps)}
+        line["forms"] = {name: run_form(name, args) for name in FORMS}
     print(json.dumps(line), flush=True)
 
 

@@ -132,11 +132,22 @@ struct TunedShape { int r, geom, k, rows; };
 const TunedShape kTuned[] = {{1, GEOM_S128, 2, 0}, {1, GEOM_64x48, 3, 0},
                              {2, GEOM_S128, 2, 0}, {2, GEOM_64x48, 2, 0},
                              {3, GEOM_S128, 1, 0}, {3, GEOM_64x48, 2, 0},
-                             {4, GEOM_S192, 1, 32}, {4, GEOM_64x48, 1, 0},
+                             {4, GEOM_S192, 1, 0}, {4, GEOM_64x48, 1, 0},
                              {5, GEOM_S128, 1, 0}, {5, GEOM_64x60, 1, 0},
                              {8, GEOM_S192, 1, 0}, {8, GEOM_64x48, 1, 0},
                              {10, GEOM_S192, 1, 0}, {10, GEOM_64x60, 1, 0},
                              {16, GEOM_S192, 1, 0}, {16, GEOM_128x64, 1, 0}};
+
+// Images below 2^20 plane-pixels are launch- and latency-bound: a few short
+// launches of the tiled kernel with several fused sweeps beat the streaming
+// kernel, whose few workgroups then run long serial chains of steps.
+// Measured on MI355X, T=10, FP32, over 1x64^2, 1x128x160, 1x256^2,
+// 3x300x400, 1x700x900 and 3x512^2: the plan with the smallest worst-case
+// ratio to each shape's fastest (within 1.14-1.42x of it everywhere; the
+// large-image table was up to 4.6x slower).
+const TunedShape kTunedSmall[] = {{1, GEOM_64x32, 5, 0}, {2, GEOM_64x48, 5, 0}, {3, GEOM_64x48, 4, 0},
+                                  {4, GEOM_64x48, 3, 0}, {5, GEOM_64x48, 2, 0}, {8, GEOM_64x48, 2, 0},
+                                  {10, GEOM_64x48, 1, 0}, {16, GEOM_128x64, 1, 0}};
 
 // Autotune cache: (device, radius, dtype, size class) -> plan measured by
 // osbf_autotune.  Guarded by a mutex; every plan gives the same bits, so the
@@ -167,20 +178,21 @@ bool tuned_plan(int planes, int H, int W, int r, int T, int dtype, Plan *out) {
     return true;
 }
 
-Plan choose_plan_model(int H, int W, int r, int T);
+Plan choose_plan_model(int planes, int H, int W, int r, int T);
 
 // The launch plan: OSBF_PLAN if set, else an autotuned plan for this device
-// and problem class, else the measured table, else the cost model.
+// and problem class, else the measured table of the problem's size class,
+// else the cost model.
 Plan choose_plan(int planes, int H, int W, int r, int T, int dtype) {
     Plan p;
     if (!getenv("OSBF_PLAN") && tuned_plan(planes, H, W, r, T, dtype, &p)) return p;
-    return choose_plan_model(H, W, r, T);
+    return choose_plan_model(planes, H, W, r, T);
 }
 
 // OSBF_PLAN="geom,k[,rows]" forces a plan (tests and tuning): geom 0 is the
 // generic kernel (region chosen by cost), 1.. the fixed and streaming
 // geometries (enum Geom); rows sets the streaming kernel's rows per workgroup.
-Plan choose_plan_model(int H, int W, int r, int T) {
+Plan choose_plan_model(int planes, int H, int W, int r, int T) {
     const size_t limit = lds_limit();
     const int kmax = T > 0 ? std::min(T, 8) : 1;
     int force_geom = -1, force_k = -1, force_rows = 0;
@@ -192,6 +204,13 @@ Plan choose_plan_model(int H, int W, int r, int T) {
             force_k = std::min(force_k, kmax);
     }
     if (force_geom < 0) {
+        if (size_class(planes, H, W) == 0) {
+            for (const auto &t : kTunedSmall) {
+                if (t.r != r) continue;
+                Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
+                if (p.tw && p.lds_bytes() <= limit) return p;
+            }
+        }
         for (const auto &t : kTuned) {
             if (t.r != r) continue;
             Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
