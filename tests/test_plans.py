@@ -1,0 +1,43 @@
+"""Host-side checks of the launch-plan tables (osbf_forward_plan needs no
+device): images below 2^20 plane-pixels take the small-image table (the tiled
+kernel with several fused sweeps per launch), larger ones the row-streaming
+plans; fused sweeps never exceed T and the launch count covers T.  Every
+plan gives the same bits (the GPU tests check that); this pins which one the
+tables pick."""
+import pytest
+import torch
+
+from paper_2108_05021_amd import osbf
+
+SMALL_K = {1: 5, 2: 5, 3: 4, 4: 3, 5: 2, 8: 2, 10: 1}
+
+
+@pytest.mark.parametrize("shape", [(1, 256, 256), (3, 512, 512), (1, 64, 64), (1, 1024, 1023)])
+@pytest.mark.parametrize("r", sorted(SMALL_K))
+def test_small_images_use_tiled_plans(shape, r):
+    for T in (1, 3, 10, 30):
+        p = osbf.forward_plan(*shape, torch.float32, r, T)
+        assert p["tile"][1] > 0, (shape, r, T, p)   # tiled: explicit tile height
+        assert p["fused"] == min(SMALL_K[r], T), (shape, r, T, p)
+        assert p["launches"] == -(-T // p["fused"])
+        assert p["tile"][0] % r == 0 and p["tile"][1] % r == 0
+
+
+@pytest.mark.parametrize("shape", [(1, 1024, 1024), (3, 2048, 2048), (1, 4096, 300)])
+@pytest.mark.parametrize("r", sorted(SMALL_K))
+def test_large_images_use_streaming_plans(shape, r):
+    for T in (1, 2, 30):
+        p = osbf.forward_plan(*shape, torch.float32, r, T)
+        assert p["tile"][1] == 0, (shape, r, T, p)  # streaming: rows chosen at launch
+        assert p["fused"] == (min(2, T) if r <= 2 else 1), (shape, r, T, p)
+        assert p["launches"] == -(-T // p["fused"])
+
+
+def test_plan_override_from_environment(monkeypatch):
+    monkeypatch.setenv("OSBF_PLAN", "5,1,32")
+    p = osbf.forward_plan(1, 256, 256, torch.float32, 2, 10)
+    assert p == {"tile": (124, 32), "fused": 1, "launches": 10}   # 128 lanes - 2r, 32 rows
+    monkeypatch.setenv("OSBF_PLAN", "1,4")
+    p = osbf.forward_plan(3, 2048, 2048, torch.float32, 3, 10)
+    # 64 x 48 region less 2kr of halo each way, rounded down to whole blocks of r
+    assert p == {"tile": (39, 24), "fused": 4, "launches": 3}
