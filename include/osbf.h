@@ -288,7 +288,10 @@ size_t osbf3d_forward_workspace_size(int32_t volumes, int32_t depth, int32_t hei
  *              (one FP32 volume set; needed when iterations >= 2 or in place)
  * Stream-ordered and asynchronous; arguments are checked before any launch.
  * Arithmetic is FP32 (sums, selection and means); results match an FP64
- * evaluation up to FP32 rounding and near-tie selections.
+ * evaluation up to FP32 rounding and near-tie selections.  The workgroup
+ * size (512 threads, 1024 at r = 4) sets where the vertical running sums
+ * restart, so OSBF_3D_THREADS=512|1024 in the environment (tests, sweeps)
+ * can change the last bits at r = 3.
  */
 osbf_status osbf3d_forward(const float *src, float *dst, int32_t volumes, int32_t depth,
                            int32_t height, int32_t width, int32_t radius, int32_t iterations,

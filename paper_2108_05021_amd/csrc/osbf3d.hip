@@ -6,8 +6,9 @@
 //   octant (sx,sy,sz) = sum over the sz side in z of the planar quadrant (sx,sy)
 //   half +-x / +-y    = sum over the full z range of the planar half
 //   half +-z          = sum over the z side of the planar (2r+1)^2 box
-// A workgroup owns a TW x TH column of voxels and a chunk of slices, and
-// streams through the slices (2.5D blocking): per slice it loads the clamped
+// A workgroup (512 or 1024 threads, TH = threads / 64 rows) owns a TW x TH
+// column of voxels and a chunk of slices, and streams through the slices
+// (2.5D blocking): per slice it loads the clamped
 // planar region into LDS, forms the planar running-sum fields V, Q, H of the
 // planar kernels, and every thread derives the nine planar quantities of its
 // (x, y) column (4 quadrants, 4 halves, the box) into a register ring of the
@@ -25,11 +26,16 @@
 #include "osbf_fwd_device.h"
 #include "osbf_internal.h"
 
+#include <cstdlib>
+
 namespace osbf {
 
 // Q on columns [xa, xb+R), rows [ya, yb+R) and H on the same columns, rows
 // [ya, yb), like fixed_phase_qh, but with (row, block of R columns) work items
-// spread over all lanes: the 3D region is only TH + 2R rows tall.
+// spread over all lanes: the 3D region is only TH + 2R rows tall.  Blocks run
+// fastest, so a wave's lanes read and write along rows (stride R within a
+// row, an odd pitch between rows): with rows fastest, lanes one row and one
+// block apart hit the same bank.
 template <int R, int RW, int NT, bool CL>
 __device__ __forceinline__ void phase_qh_items(const float *P, const float *V, float *Q, float *Hs,
                                                int tid, int ox, int oy, int W, int xa, int xb,
@@ -39,9 +45,9 @@ __device__ __forceinline__ void phase_qh_items(const float *P, const float *V, f
     const int nr = yend - ya, nb = (xend - xa + R - 1) / R;
     const int lo = CL ? max(0, xa - R) : xa - R;
     const int hi = CL ? min(W, xend) - 1 : xend - 1;
-    const int dr = NT % nr, db = NT / nr;
-    int b = tid / nr, row = tid - b * nr;
-    while (b < nb) {
+    const int db = NT % nb, dr = NT / nb;
+    int row = tid / nb, b = tid - row * nb;
+    while (row < nr) {
         const int y = ya + row;
         const bool doH = y < yb;
         const int x0 = xa + b * R;
@@ -70,11 +76,11 @@ __device__ __forceinline__ void phase_qh_items(const float *P, const float *V, f
                 if (doH) Hs[rb + x0 + t] = h;
             }
         }
-        row += dr;
         b += db;
-        if (row >= nr) {
-            row -= nr;
-            ++b;
+        row += dr;
+        if (b >= nb) {
+            b -= nb;
+            ++row;
         }
     }
 }
@@ -272,24 +278,44 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
     }
 }
 
+
 bool fwd3d_radius(int r) { return r >= 1 && r <= 4; }
 
-void fwd3d_geometry(int r, int *tw, int *th) {
-    *tw = 64 - 2 * r;
-    *th = 512 / 64;
+// 1024 threads (16-row tiles) halve the planar halo rows per output row;
+// measured faster only at r = 4 (98 K against 75 K MVox·it/s on 256^3; at
+// r = 4 the 512-thread kernel's 139 VGPRs also leave 3 waves per SIMD), and
+// slower at r = 1..3 (186 K / 133 K / 113 K against 193 K / 178 K / 127 K).
+int fwd3d_threads(int r) {
+    if (const char *env = getenv("OSBF_3D_THREADS")) {
+        const int n = atoi(env);
+        if (n == 512 || n == 1024) return n;
+    }
+    return r >= 4 ? 1024 : 512;
 }
 
-size_t fwd3d_lds_bytes(int r) { return (size_t)6 * (512 / 64 + 2 * r) * 65 * sizeof(float); }
+void fwd3d_geometry(int r, int threads, int *tw, int *th) {
+    *tw = 64 - 2 * r;
+    *th = threads / 64;
+}
+
+size_t fwd3d_lds_bytes(int r, int threads) { return (size_t)6 * (threads / 64 + 2 * r) * 65 * sizeof(float); }
+
+template <int R, int NT>
+static hipError_t launch3d_nt(const Fwd3dLaunch &a, hipStream_t stream) {
+    const int blocks = a.tiles_x * a.tiles_y * a.chunks * a.vols;
+    const size_t lds = fwd3d_lds_bytes(R, NT);
+    if (a.sel)
+        hipLaunchKernelGGL((fwd3d_kernel<R, NT, true>), dim3(blocks), dim3(NT), lds, stream, a);
+    else
+        hipLaunchKernelGGL((fwd3d_kernel<R, NT, false>), dim3(blocks), dim3(NT), lds, stream, a);
+    return hipGetLastError();
+}
 
 template <int R>
 static hipError_t launch3d(const Fwd3dLaunch &a, hipStream_t stream) {
-    const int blocks = a.tiles_x * a.tiles_y * a.chunks * a.vols;
-    const size_t lds = fwd3d_lds_bytes(R);
-    if (a.sel)
-        hipLaunchKernelGGL((fwd3d_kernel<R, 512, true>), dim3(blocks), dim3(512), lds, stream, a);
-    else
-        hipLaunchKernelGGL((fwd3d_kernel<R, 512, false>), dim3(blocks), dim3(512), lds, stream, a);
-    return hipGetLastError();
+    if (a.threads == 1024) return launch3d_nt<R, 1024>(a, stream);
+    if (a.threads == 512) return launch3d_nt<R, 512>(a, stream);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_forward3d(const Fwd3dLaunch &a, hipStream_t stream) {

@@ -828,7 +828,8 @@ osbf_status osbf3d_forward(const float *src, float *dst, int32_t vols, int32_t D
 
     Fwd3dLaunch a;
     int th;
-    fwd3d_geometry(r, &a.tw, &th);
+    a.threads = fwd3d_threads(r);
+    fwd3d_geometry(r, a.threads, &a.tw, &th);
     a.vols = vols; a.D = D; a.H = H; a.W = W; a.r = r;
     a.tiles_x = (W + a.tw - 1) / a.tw;
     a.tiles_y = (H + th - 1) / th;

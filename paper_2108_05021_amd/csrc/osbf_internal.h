@@ -76,18 +76,22 @@ hipError_t launch_batched_round(int dtype, int maxr, const FwdLaunch *descs, con
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t s);
 
 // One sweep of the volume filter over every volume: a workgroup per
-// (volume, slice chunk, tile); tiles are tw x 8 voxel columns.
+// (volume, slice chunk, tile); tiles are tw x (threads / 64) voxel columns.
 struct Fwd3dLaunch {
     const float *src;     // [vols][D][H][W]
     float *dst;           // [vols][D][H][W], never aliases src
     uint8_t *sel;         // nullable [vols][D][H][W] map of this sweep
     int vols, D, H, W, r;
+    int threads;          // workgroup size: 512 or 1024
     int tw, tiles_x, tiles_y;
     int zc, chunks;       // slices per workgroup, chunks per volume
 };
 bool fwd3d_radius(int r);
-void fwd3d_geometry(int r, int *tw, int *th);
-size_t fwd3d_lds_bytes(int r);
+// Workgroup size for radius r (OSBF_3D_THREADS=512|1024 overrides) and the
+// tile it owns.
+int fwd3d_threads(int r);
+void fwd3d_geometry(int r, int threads, int *tw, int *th);
+size_t fwd3d_lds_bytes(int r, int threads);
 hipError_t launch_forward3d(const Fwd3dLaunch &a, hipStream_t s);
 
 // One sweep of the one-sided Gaussian filter over every plane.

@@ -49,7 +49,12 @@ def _vol(shape, seed, K=6, sigma=0.05):
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 70), (5, 9, 9), (3, 17, 130), (40, 37, 121),
                                    (70, 20, 30), (2, 6, 11, 13)])
 @pytest.mark.parametrize("r", [1, 2, 3, 4])
-def test_sweep_parity(dev, shape, r):
+@pytest.mark.parametrize("threads", [None, "512", "1024"])
+def test_sweep_parity(dev, monkeypatch, shape, r, threads):
+    """Teacher-forced sweeps against the oracle, with the default workgroup
+    size for r and with both sizes forced (tiles of 8 and 16 rows)."""
+    if threads is not None:
+        monkeypatch.setenv("OSBF_3D_THREADS", threads)
     x = torch.from_numpy(_vol(shape, 100 + r + len(shape))).to(dev)
     flips = 0
     cur = x
