@@ -360,18 +360,19 @@ static hipError_t launch_gs(const GaussLaunch &a, hipStream_t stream) {
     if (a.th <= 0) {
         // rows per workgroup such that the strips' chunks fill the device's
         // resident workgroup slots once
-        static std::atomic<int> slots[64];  // per device; 0 = not yet queried
+        static std::atomic<int> slots[2][64];  // per kernel (maps or not) and device; 0 = not yet queried
+        const int ks = a.sel ? 1 : 0;
         int dev = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
-        int n = dev < 64 ? slots[dev].load(std::memory_order_relaxed) : 0;
+        int n = dev < 64 ? slots[ks][dev].load(std::memory_order_relaxed) : 0;
         if (!n) {
             int cus = 0, per_cu = 0;
             e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, RW, lds);
             if (e != hipSuccess) return e;
             n = std::max(1, cus * per_cu);
-            if (dev < 64) slots[dev].store(n, std::memory_order_relaxed);
+            if (dev < 64) slots[ks][dev].store(n, std::memory_order_relaxed);
         }
         const long long strips = (long long)a.tiles_x * a.planes;
         const int per_strip = (int)std::max<long long>(1, n / strips);
