@@ -237,9 +237,10 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osb
  *              dtype; src is read, dst is overwritten (scratch)
  * Times every fixed LDS geometry and fusion depth that fits, the
  * row-streaming kernel's strip widths with a few row counts per workgroup,
- * and the cost model's generic plan, with HIP events, a few launches each,
- * on `stream`,
- * and blocks until done (do not call during stream capture).  The winner is
+ * and the cost model's generic plan, with HIP events on `stream`: the
+ * candidates back to back, eight launches each, best of three rounds.  The
+ * plan the measured tables would use is kept unless another is more than
+ * 3% faster.  Blocks until done (do not call during stream capture).  The winner is
  * cached per (device, radius, dtype, size class: planes*height*width below or
  * at least 2^20) and used by later osbf_forward / osbf_backward /
  * osbf_forward_plan calls of that class (batches keep their own work

@@ -966,36 +966,56 @@ osbf_status osbf_autotune(const void *src, void *dst, int32_t planes, int32_t H,
         if (best.tw) cands.push_back(best);
     }
     if (cands.empty()) return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
-    hipEvent_t e0, e1;
-    hipError_t e;
-    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event");
-    if ((e = hipEventCreate(&e1)) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return hip_fail(e, "event");
+    // the plan osbf_forward would use without tuning (the measured tables)
+    size_t incumbent = cands.size();
+    if (!getenv("OSBF_PLAN")) {
+        const Plan t = choose_plan_model(planes, H, W, r, T);
+        for (size_t c = 0; c < cands.size() && incumbent == cands.size(); ++c)
+            if (cands[c].geom == t.geom && cands[c].k == t.k && cands[c].tw == t.tw &&
+                plan_rows(cands[c], r) == plan_rows(t, r))
+                incumbent = c;
+        if (incumbent == cands.size() && t.tw && t.lds_bytes() <= limit) cands.push_back(t);
     }
-    Plan best;
-    double best_ms = 1e300;
-    constexpr int kReps = 3;
-    for (const Plan &p : cands) {
-        // one warm-up launch, then kReps timed launches of k sweeps each
-        e = enqueue_forward(p, p.k, src, dst, nullptr, planes, H, W, r, dtype, stream);
-        if (e == hipSuccess) e = hipEventRecord(e0, stream);
-        for (int i = 0; i < kReps && e == hipSuccess; ++i)
+    // Every candidate gets its own event pair and a round is synchronised
+    // once at its end, so the device runs the candidates back to back, as it
+    // runs the sweeps of a call (a sync per candidate leaves it idle between
+    // bursts and skews short measurements).  A warm-up burst first, then
+    // kRounds rounds, each timing kReps launches of k sweeps per candidate after one
+    // untimed launch; a candidate's figure is its best round.  Short bursts
+    // still vary by several percent from run to run, so the plan the tables
+    // would choose stays unless another beats it by more than 3%.
+    constexpr int kReps = 8, kRounds = 3, kWarm = 8;
+    const size_t nc = cands.size();
+    std::vector<hipEvent_t> ev(2 * nc, nullptr);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (int i = 0; i < kWarm && e == hipSuccess; ++i)
+        e = enqueue_forward(cands[0], cands[0].k, src, dst, nullptr, planes, H, W, r, dtype, stream);
+    std::vector<double> per_sweep(nc, 1e300);
+    for (int round = 0; round < kRounds && e == hipSuccess; ++round) {
+        for (size_t c = 0; c < nc && e == hipSuccess; ++c) {
+            const Plan &p = cands[c];
             e = enqueue_forward(p, p.k, src, dst, nullptr, planes, H, W, r, dtype, stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return hip_fail(e, "autotune launch");
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * c], stream);
+            for (int i = 0; i < kReps && e == hipSuccess; ++i)
+                e = enqueue_forward(p, p.k, src, dst, nullptr, planes, H, W, r, dtype, stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 1], stream);
         }
-        const double per_sweep = ms / (kReps * p.k);
-        if (per_sweep < best_ms) { best_ms = per_sweep; best = p; }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2 * nc - 1]);
+        for (size_t c = 0; c < nc && e == hipSuccess; ++c) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]);
+            if (e == hipSuccess) per_sweep[c] = std::min(per_sweep[c], (double)ms / (kReps * cands[c].k));
+        }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (hipEvent_t v : ev)
+        if (v) (void)hipEventDestroy(v);
+    if (e != hipSuccess) return hip_fail(e, "autotune launch");
+    size_t pick = 0;
+    for (size_t c = 1; c < nc; ++c)
+        if (per_sweep[c] < per_sweep[pick]) pick = c;
+    if (pick != incumbent && incumbent < nc && per_sweep[pick] > 0.97 * per_sweep[incumbent]) pick = incumbent;
+    const Plan best = cands[pick];
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "device");
     {
