@@ -94,6 +94,26 @@ def measured_traffic(config_key: str, plans):
     return d.get("per_launch_bytes", {}).get(config_key)
 
 
+# VALU issue peak with packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz lane-operations per second
+VALU_PEAK_TLANE_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def measured_valu(plans):
+    """VALU lane-operations per pixel-sweep by radius from the committed
+    rocprofv3 SQ_INSTS_VALU record, if it was taken on the current forward
+    kernel sources with the same launch plans (else None)."""
+    path = os.path.join(ROOT, "profiles", "fwd_valu.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_source_hash() or d.get("plans") != plan_signature(plans):
+        return None
+    ops = d.get("lane_ops_per_px_sweep", {})
+    return {int(r): float(v) for r, v in ops.items()}
+
+
 def cpu_baseline(img, budget_s: float = 10.0):
     """The FP64 oracle on the host: the whole bench image (all planes), as
     many consecutive sweeps per radius as fit in budget_s / 3 seconds (at
@@ -462,6 +482,16 @@ def main():
         tot_ms += per_r_ms[r]
     achieved = tot_bytes / (tot_ms / 1e3) / 1e9
     traffic = measured_traffic("rgb2048_T30", plans)
+    # the kernels' own bound: VALU issue (lane-operations measured per
+    # pixel-sweep, times the pixel-sweeps of each radius, over its time)
+    valu = measured_valu(plans)
+    alu = None
+    if valu and all(r in valu for r in RADII):
+        ops = sum(valu[r] * C * H * W * T_SWEEPS for r in RADII)
+        a_t = ops / (tot_ms / 1e3) / 1e12
+        alu = {"achieved": round(a_t, 2), "peak": round(VALU_PEAK_TLANE_OPS, 2), "unit": "Tlane-op/s",
+               "frac": round(a_t / VALU_PEAK_TLANE_OPS, 4),
+               "lane_ops_per_px_sweep": {str(r): valu[r] for r in RADII}}
 
     line = {
         "metric": "megapixel-iterations/s (fwd, batched, fwd+bwd) and % of HBM peak",
@@ -482,7 +512,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": " + ".join(dict.fromkeys(k["kernel"] for k in kernels)), "kernels": kernels,
-                     "bytes_per_px_sweep": BYTES_PER_PX_SWEEP},
+                     "bytes_per_px_sweep": BYTES_PER_PX_SWEEP, "valu_issue": alu},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(img)
