@@ -604,7 +604,9 @@ struct BatchLayout {
 };
 
 // Rows per work item: long enough that the r halo rows a chunk recomputes
-// stay small, short enough that a round has many items to balance.
+// stay small, short enough that a round has many items to balance (the
+// 256-image mixed batch: 32 rows 324 K, 64 rows 340 K, 128 rows 330 K
+// MPix*it/s).
 constexpr int kBatchRows = 64;
 
 osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchLayout *L) {
