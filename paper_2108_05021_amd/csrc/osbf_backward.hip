@@ -625,7 +625,12 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
 // at r <= 5) need more registers and LDS and measured 10-25% slower.
 constexpr int adj_step_blocks(int) { return 1; }
 
-constexpr int kAdjStreamLanes = 128, kAdjStreamRows = 64;
+// Output rows per workgroup: short chunks give many independent workgroups
+// per CU, which hides the step barriers and the loads better than fewer long
+// walks (32x3x512^2, 5 adjoint sweeps, MPix*it/s at 64 / 24 rows: r=3
+// 257 K / 301 K, r=5 239 K / 263 K, r=10 132 K / 143 K; 8 rows is slower
+// again, the 2r warm-up rows of each chunk then dominate).
+constexpr int kAdjStreamLanes = 128, kAdjStreamRows = 24;
 
 static size_t adjoint_stream_lds_bytes(int r) {
     return (size_t)4 * adj_step_blocks(r) * r * (kAdjStreamLanes + 1) * sizeof(float);
