@@ -647,8 +647,8 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
     off = align256(off + (size_t)L->rounds * n * sizeof(FwdLaunch));
     L->items_off = off;
     off = align256(off + (size_t)L->rounds * L->max_items * sizeof(uint2));
-    L->counts_off = off;
-    off = align256(off + (size_t)std::max(L->rounds, 1) * sizeof(int));
+    L->counts_off = off;  // per round: items of radius above 2, then of radius 1 and 2
+    off = align256(off + (size_t)2 * std::max(L->rounds, 1) * sizeof(int));
     L->bufs_off = off;
     for (int j = 0; j < n; ++j) {
         L->buf_off[j] = off;
@@ -686,7 +686,7 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
     // host tables
     std::vector<FwdLaunch> descs((size_t)L.rounds * n);
     std::vector<uint2> items((size_t)L.rounds * L.max_items);
-    std::vector<int> counts(std::max(L.rounds, 1), 0);
+    std::vector<int> counts((size_t)2 * std::max(L.rounds, 1), 0);
     // images in decreasing cost order (radius) for the work lists
     std::vector<int> order;
     for (int j = 0; j < n; ++j)
@@ -715,16 +715,22 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
             cur = out;
         }
     }
+    // a round's items: radius above 2 first (decreasing radius), then radius
+    // 1 and 2, each part run by its own kernel class
+    bool any_big = false, any_small = false;
+    for (int j : order) (imgs[j].radius > 2 ? any_big : any_small) = true;
     for (int r = 0; r < L.rounds; ++r) {
         uint2 *it = items.data() + (size_t)r * L.max_items;
-        int c = 0;
+        int c = 0, c_big = 0;
         for (int j : order) {
             if (r >= L.img[j].rounds) continue;
             const FwdLaunch &a = descs[(size_t)r * n + j];
             const int cnt = a.tiles_x * a.tiles_y * a.planes;
             for (int w = 0; w < cnt; ++w) it[c++] = make_uint2((unsigned)j, (unsigned)w);
+            if (a.r > 2) c_big = c;
         }
-        counts[r] = c;
+        counts[2 * r] = c_big;
+        counts[2 * r + 1] = c - c_big;
     }
     hipError_t e;
     if (L.rounds) {
@@ -732,15 +738,19 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
                                 hipMemcpyHostToDevice, stream)) != hipSuccess ||
             (e = hipMemcpyAsync((char *)ws + L.items_off, items.data(), items.size() * sizeof(uint2),
                                 hipMemcpyHostToDevice, stream)) != hipSuccess ||
-            (e = hipMemcpyAsync((char *)ws + L.counts_off, counts.data(), L.rounds * sizeof(int),
+            (e = hipMemcpyAsync((char *)ws + L.counts_off, counts.data(), (size_t)2 * L.rounds * sizeof(int),
                                 hipMemcpyHostToDevice, stream)) != hipSuccess)
             return hip_fail(e, "upload batch tables");
         // the host vectors go out of scope: wait for the copies
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "synchronize");
     }
-    int slots = 0;
-    if (L.rounds && (e = batched_slots((int)dtype, L.maxr, &slots)) != hipSuccess) return hip_fail(e, "occupancy");
+    int slots = 0, slots_small = 0;
+    if (L.rounds && any_big && (e = batched_slots((int)dtype, L.maxr, &slots)) != hipSuccess)
+        return hip_fail(e, "occupancy");
+    if (L.rounds && any_small && (e = batched_slots((int)dtype, 2, &slots_small)) != hipSuccess)
+        return hip_fail(e, "occupancy");
     const int64_t g = std::min<int64_t>(L.max_items, std::max(slots, 1));
+    const int64_t gs = std::min<int64_t>(L.max_items, std::max(slots_small, 1));
     memset(batch, 0, sizeof *batch);
     batch->n = n;
     batch->dtype = dtype;
@@ -753,7 +763,8 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
     batch->items_off = L.items_off;
     batch->counts_off = L.counts_off;
     batch->identity = L.identity;
-    batch->reserved[0] = L.maxr;  // kernel class and LDS of the rounds
+    batch->reserved[0] = any_big ? L.maxr : 0;  // class of the radius > 2 launches (0: none)
+    batch->reserved[1] = any_small ? (int)std::max<int64_t>(8, (gs + 7) / 8 * 8) : 0;  // grid of the radius <= 2 launches
     // identity images are copied at launch: remember them in the tables is
     // not needed; the launch re-reads the host list through the caller.
     return OSBF_SUCCESS;
@@ -769,8 +780,15 @@ osbf_status osbf_batched_launch(const osbf_batch *batch, void *stream_) {
     const uint2 *items = (const uint2 *)((const char *)batch->ws + batch->items_off);
     const int *counts = (const int *)((const char *)batch->ws + batch->counts_off);
     for (int r = 0; r < batch->rounds; ++r) {
-        hipError_t e = launch_batched_round(batch->dtype, batch->reserved[0], descs + (size_t)r * batch->n,
-                                            items + (size_t)r * batch->max_items, counts + r, batch->grid, stream);
+        const FwdLaunch *d = descs + (size_t)r * batch->n;
+        const uint2 *it = items + (size_t)r * batch->max_items;
+        hipError_t e = hipSuccess;
+        if (batch->reserved[0])  // radius above 2
+            e = launch_batched_round(batch->dtype, batch->reserved[0], d, it, nullptr, counts + 2 * r, batch->grid,
+                                     stream);
+        if (e == hipSuccess && batch->reserved[1])  // radius 1 and 2, after the others in the list
+            e = launch_batched_round(batch->dtype, 2, d, it, counts + 2 * r, counts + 2 * r + 1, batch->reserved[1],
+                                     stream);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
     return OSBF_SUCCESS;

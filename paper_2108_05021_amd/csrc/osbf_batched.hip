@@ -12,8 +12,10 @@
 //
 // Every item runs the same code as the single-image streaming kernel; its
 // window sums are position-deterministic, so the batch gives the same bits as
-// filtering each image alone.  Batches whose radii are all at most 8 take a
-// kernel without the larger radii's code, which needs fewer registers.
+// filtering each image alone.  A kernel compiled for radii up to 2 needs far
+// fewer registers than one for radii up to 8 (or 16), so a round runs as two
+// launches: the items of radius above 2 (listed first) in the larger class,
+// then those of radius 1 and 2 in the small one.
 #include "osbf_stream_device.h"
 
 namespace osbf {
@@ -25,10 +27,18 @@ __device__ __forceinline__ void batched_item(const FwdLaunch &a, int t, float *l
     switch (a.r) {
     case 1: fwd_stream_item<DT, 1, kBatchLanes, stream_step_rows(1), false, MODE_EXACT>(a, t, lds); break;
     case 2: fwd_stream_item<DT, 2, kBatchLanes, stream_step_rows(2), false, MODE_EXACT>(a, t, lds); break;
-    case 3: fwd_stream_item<DT, 3, kBatchLanes, stream_step_rows(3), false, MODE_EXACT>(a, t, lds); break;
-    case 4: fwd_stream_item<DT, 4, kBatchLanes, stream_step_rows(4), false, MODE_EXACT>(a, t, lds); break;
-    case 5: fwd_stream_item<DT, 5, kBatchLanes, stream_step_rows(5), false, MODE_EXACT>(a, t, lds); break;
-    case 8: fwd_stream_item<DT, 8, kBatchLanes, stream_step_rows(8), false, MODE_EXACT>(a, t, lds); break;
+    case 3:
+        if constexpr (MAXR >= 3) fwd_stream_item<DT, 3, kBatchLanes, stream_step_rows(3), false, MODE_EXACT>(a, t, lds);
+        break;
+    case 4:
+        if constexpr (MAXR >= 4) fwd_stream_item<DT, 4, kBatchLanes, stream_step_rows(4), false, MODE_EXACT>(a, t, lds);
+        break;
+    case 5:
+        if constexpr (MAXR >= 5) fwd_stream_item<DT, 5, kBatchLanes, stream_step_rows(5), false, MODE_EXACT>(a, t, lds);
+        break;
+    case 8:
+        if constexpr (MAXR >= 8) fwd_stream_item<DT, 8, kBatchLanes, stream_step_rows(8), false, MODE_EXACT>(a, t, lds);
+        break;
     case 10:
         if constexpr (MAXR >= 10) fwd_stream_item<DT, 10, kBatchLanes, stream_step_rows(10), false, MODE_EXACT>(a, t, lds);
         break;
@@ -40,12 +50,14 @@ __device__ __forceinline__ void batched_item(const FwdLaunch &a, int t, float *l
 }
 
 // descs: this round's per-image launch descriptors; items: (image, item)
-// pairs of this round; count: number of items.
+// pairs of this round; skip (nullable): items of the round before this
+// launch's share; count: number of items of this launch.
 template <int DT, int MAXR>
 __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(stream_min_waves(MAXR))))
-void batched_round_kernel(const FwdLaunch *descs, const uint2 *items, const int *count) {
+void batched_round_kernel(const FwdLaunch *descs, const uint2 *items, const int *skip, const int *count) {
     extern __shared__ float lds[];
     const int n = *count;
+    if (skip) items += *skip;
     const int nx = gridDim.x >> 3;           // workgroups per XCD (grid is a multiple of 8)
     const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3;
     const int chunk = (n + 7) >> 3;
@@ -82,8 +94,10 @@ static const void *batched_fn(int dtype) {
     }
 }
 
+// Kernel classes by the largest radius they run: 2 (71 VGPRs, 7 waves per
+// SIMD), 8 (122, 4 waves) and 16.
 static const void *batched_function(int dtype, int maxr) {
-    return maxr <= 8 ? batched_fn<8>(dtype) : batched_fn<16>(dtype);
+    return maxr <= 2 ? batched_fn<2>(dtype) : maxr <= 8 ? batched_fn<8>(dtype) : batched_fn<16>(dtype);
 }
 
 // Resident workgroups of the round kernel on the current device.
@@ -102,14 +116,14 @@ hipError_t batched_slots(int dtype, int maxr, int *slots) {
 }
 
 hipError_t launch_batched_round(int dtype, int maxr, const FwdLaunch *descs, const uint2 *items,
-                                const int *count, int grid, hipStream_t stream) {
+                                const int *skip, const int *count, int grid, hipStream_t stream) {
     const void *fn = batched_function(dtype, maxr);
     const size_t lds = batched_lds_bytes(maxr);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    void *args[] = {(void *)&descs, (void *)&items, (void *)&count};
+    void *args[] = {(void *)&descs, (void *)&items, (void *)&skip, (void *)&count};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBatchLanes), args, lds, stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();
