@@ -630,15 +630,20 @@ constexpr int adj_step_blocks(int) { return 1; }
 // walks (32x3x512^2, 5 adjoint sweeps, MPix*it/s at 64 / 24 rows: r=3
 // 257 K / 301 K, r=5 239 K / 263 K, r=10 132 K / 143 K; 8 rows is slower
 // again, the 2r warm-up rows of each chunk then dominate).
-constexpr int kAdjStreamLanes = 128, kAdjStreamRows = 24;
+constexpr int kAdjStreamRows = 24;
+
+// Strip lanes by radius: 128, except 192 at r=3 and 256 at r=16 (32x3x512^2,
+// 24-row chunks, MPix*it/s with 128 / 192 / 256 lanes: r=3 293-299 K / 308 K
+// / 270 K, r=5 257 K / 202 K / 228 K, r=16 65 K / 62 K / 75 K).
+constexpr int adj_stream_lanes(int r) { return r == 16 ? 256 : r == 3 ? 192 : 128; }
 
 static size_t adjoint_stream_lds_bytes(int r) {
-    return (size_t)4 * adj_step_blocks(r) * r * (kAdjStreamLanes + 1) * sizeof(float);
+    return (size_t)4 * adj_step_blocks(r) * r * (adj_stream_lanes(r) + 1) * sizeof(float);
 }
 
 bool adjoint_stream_tile(int r, int *tw, int *th, size_t *lds_bytes) {
     if (!(r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 8 || r == 10 || r == 16)) return false;
-    *tw = ((kAdjStreamLanes - 4 * r) / r) * r;
+    *tw = ((adj_stream_lanes(r) - 4 * r) / r) * r;
     const int step = adj_step_blocks(r) * r;
     *th = (kAdjStreamRows + step - 1) / step * step;
     *lds_bytes = adjoint_stream_lds_bytes(r);
@@ -648,9 +653,14 @@ bool adjoint_stream_tile(int r, int *tw, int *th, size_t *lds_bytes) {
 template <int R>
 static hipError_t launch_adjoint_stream(const BwdLaunch &a, hipStream_t stream) {
     const size_t lds = adjoint_stream_lds_bytes(R);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)adjoint_stream_kernel<R, adj_stream_lanes(R), adj_step_blocks(R)>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     const int blocks = a.tiles_x * a.tiles_y * a.planes;
-    hipLaunchKernelGGL((adjoint_stream_kernel<R, kAdjStreamLanes, adj_step_blocks(R)>), dim3(blocks),
-                       dim3(kAdjStreamLanes), lds, stream, a);
+    hipLaunchKernelGGL((adjoint_stream_kernel<R, adj_stream_lanes(R), adj_step_blocks(R)>), dim3(blocks),
+                       dim3(adj_stream_lanes(R)), lds, stream, a);
     return hipGetLastError();
 }
 
