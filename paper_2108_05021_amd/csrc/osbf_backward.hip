@@ -629,7 +629,9 @@ constexpr int adj_step_blocks(int) { return 1; }
 // per CU, which hides the step barriers and the loads better than fewer long
 // walks (32x3x512^2, 5 adjoint sweeps, MPix*it/s at 64 / 24 rows: r=3
 // 257 K / 301 K, r=5 239 K / 263 K, r=10 132 K / 143 K; 8 rows is slower
-// again, the 2r warm-up rows of each chunk then dominate).
+// again, the 2r warm-up rows of each chunk then dominate).  With the 192-lane
+// strips at r=3, 18 / 24 / 30 / 36 rows time within 3% of each other, 24
+// first.
 constexpr int kAdjStreamRows = 24;
 
 // Strip lanes by radius: 128, except 192 at r=3 and 256 at r=16 (32x3x512^2,
