@@ -243,8 +243,8 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osb
  * candidates back to back, eight launches each, best of three rounds.  The
  * plan the measured tables would use is kept unless another is more than
  * 3% faster.  Blocks until done (do not call during stream capture).  The winner is
- * cached per (device, radius, dtype, size class: planes*height*width below or
- * at least 2^20) and used by later osbf_forward / osbf_backward /
+ * cached per (device, radius, dtype, size class: planes*height*width below
+ * 2^17, below 2^20, or larger) and used by later osbf_forward / osbf_backward /
  * osbf_forward_plan calls of that class (batches keep their own work
  * items); OSBF_PLAN in the environment still takes precedence.
  * Every plan computes the same bits, so tuning changes speed, never

@@ -140,14 +140,19 @@ const TunedShape kTuned[] = {{1, GEOM_S128, 2, 0}, {1, GEOM_64x48, 3, 0},
 
 // Images below 2^20 plane-pixels are launch- and latency-bound: a few short
 // launches of the tiled kernel with several fused sweeps beat the streaming
-// kernel, whose few workgroups then run long serial chains of steps.
-// Measured on MI355X, T=10, FP32, over 1x64^2, 1x128x160, 1x256^2,
-// 3x300x400, 1x700x900 and 3x512^2: the plan with the smallest worst-case
-// ratio to each shape's fastest (within 1.14-1.42x of it everywhere; the
-// large-image table was up to 4.6x slower).
-const TunedShape kTunedSmall[] = {{1, GEOM_64x32, 5, 0}, {2, GEOM_64x48, 5, 0}, {3, GEOM_64x48, 4, 0},
-                                  {4, GEOM_64x48, 3, 0}, {5, GEOM_64x48, 2, 0}, {8, GEOM_64x48, 2, 0},
-                                  {10, GEOM_64x48, 1, 0}, {16, GEOM_128x64, 1, 0}};
+// kernel, whose few workgroups then run long serial chains of steps.  Two
+// tables, measured on MI355X at T=10, FP32: below 2^17 plane-pixels (1x64^2,
+// 1x128x160, 1x256^2) and from 2^17 to 2^20 (3x300x400, 1x700x900,
+// 3x512^2); each entry is the plan with the smallest worst-case ratio to each
+// shape's fastest (within 1.0-1.15x of it below 2^17 and 1.05-1.24x above,
+// where one table for both ranges was up to 1.42x slower and the large-image
+// table up to 4.6x).
+const TunedShape kTunedTiny[] = {{1, GEOM_64x32, 8, 0}, {2, GEOM_64x32, 6, 0}, {3, GEOM_64x48, 6, 0},
+                                 {4, GEOM_64x48, 4, 0}, {5, GEOM_64x60, 4, 0}, {8, GEOM_64x48, 2, 0},
+                                 {10, GEOM_64x60, 2, 0}, {16, GEOM_64x60, 1, 0}};
+const TunedShape kTunedSmall[] = {{1, GEOM_64x48, 6, 0}, {2, GEOM_64x60, 5, 0}, {3, GEOM_64x60, 3, 0},
+                                  {4, GEOM_64x60, 2, 0}, {5, GEOM_64x60, 2, 0}, {8, GEOM_64x60, 1, 0},
+                                  {10, GEOM_64x60, 1, 0}, {16, GEOM_128x64, 1, 0}};
 
 // Autotune cache: (device, radius, dtype, size class) -> plan measured by
 // osbf_autotune.  Guarded by a mutex; every plan gives the same bits, so the
@@ -155,7 +160,11 @@ const TunedShape kTunedSmall[] = {{1, GEOM_64x32, 5, 0}, {2, GEOM_64x48, 5, 0}, 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, Plan> g_tune;
 
-int size_class(int planes, int H, int W) { return (long long)planes * H * W >= (1LL << 20) ? 1 : 0; }
+// 0: below 2^17 plane-pixels, 1: below 2^20, 2: larger.
+int size_class(int planes, int H, int W) {
+    const long long px = (long long)planes * H * W;
+    return px < (1LL << 17) ? 0 : px < (1LL << 20) ? 1 : 2;
+}
 
 // Rows per workgroup of a plan (the streaming kernel rounds to whole steps;
 // 0: chosen at launch so that the chunks fill the device's resident
@@ -204,8 +213,9 @@ Plan choose_plan_model(int planes, int H, int W, int r, int T) {
             force_k = std::min(force_k, kmax);
     }
     if (force_geom < 0) {
-        if (size_class(planes, H, W) == 0) {
-            for (const auto &t : kTunedSmall) {
+        const int cls = size_class(planes, H, W);
+        if (cls < 2) {
+            for (const auto &t : cls == 0 ? kTunedTiny : kTunedSmall) {
                 if (t.r != r) continue;
                 Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
                 if (p.tw && p.lds_bytes() <= limit) return p;

@@ -1,7 +1,7 @@
 """Host-side checks of the launch-plan tables (osbf_forward_plan needs no
-device): images below 2^20 plane-pixels take the small-image table (the tiled
-kernel with several fused sweeps per launch), larger ones the row-streaming
-plans; fused sweeps never exceed T and the launch count covers T.  Every
+device): images below 2^17 and below 2^20 plane-pixels take the two
+small-image tables (the tiled kernel with several fused sweeps per launch),
+larger ones the row-streaming plans; fused sweeps never exceed T and the launch count covers T.  Every
 plan gives the same bits (the GPU tests check that); this pins which one the
 tables pick."""
 import pytest
@@ -9,16 +9,21 @@ import torch
 
 from paper_2108_05021_amd import osbf
 
-SMALL_K = {1: 5, 2: 5, 3: 4, 4: 3, 5: 2, 8: 2, 10: 1}
+TINY_K = {1: 8, 2: 6, 3: 6, 4: 4, 5: 4, 8: 2, 10: 2}   # below 2^17 plane-pixels
+SMALL_K = {1: 6, 2: 5, 3: 3, 4: 2, 5: 2, 8: 1, 10: 1}  # 2^17 up to 2^20
+SMALL_SHAPES = {(1, 256, 256): TINY_K, (1, 64, 64): TINY_K, (1, 128, 160): TINY_K, (1, 362, 362): TINY_K,
+                (3, 512, 512): SMALL_K, (1, 1024, 1023): SMALL_K, (3, 300, 400): SMALL_K,
+                (2, 256, 256): SMALL_K}
 
 
-@pytest.mark.parametrize("shape", [(1, 256, 256), (3, 512, 512), (1, 64, 64), (1, 1024, 1023)])
+@pytest.mark.parametrize("shape", sorted(SMALL_SHAPES))
 @pytest.mark.parametrize("r", sorted(SMALL_K))
 def test_small_images_use_tiled_plans(shape, r):
+    table = SMALL_SHAPES[shape]
     for T in (1, 3, 10, 30):
         p = osbf.forward_plan(*shape, torch.float32, r, T)
         assert p["tile"][1] > 0, (shape, r, T, p)   # tiled: explicit tile height
-        assert p["fused"] == min(SMALL_K[r], T), (shape, r, T, p)
+        assert p["fused"] == min(table[r], T), (shape, r, T, p)
         assert p["launches"] == -(-T // p["fused"])
         assert p["tile"][0] % r == 0 and p["tile"][1] % r == 0
 
