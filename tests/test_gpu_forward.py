@@ -114,6 +114,26 @@ def test_fused_sweeps(dev, r, T, tile, k):
     replay_check_planes(img, yf.cpu().numpy(), self_f.cpu().numpy(), r, max_outliers=0)
 
 
+@pytest.mark.parametrize("shape", [(1, 362, 362), (2, 256, 256)])  # just below / at 2^17 plane-pixels
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8, 10, 16])
+def test_small_image_table_plans(dev, shape, r):
+    """The plan tables for images below 2^20 plane-pixels (tiled, several
+    sweeps fused per launch, one table below 2^17 and one above) give the
+    bits and maps of single-sweep launches of the generic kernel, and the
+    oracle replaying the maps reproduces them."""
+    T = 9
+    rng = np.random.default_rng(300 + r + shape[0])
+    img = synth.voronoi(shape[1], shape[2], 12, 0.05, rng, C=shape[0])
+    x = _gpu(img, dev)
+    p = osbf.forward_plan(*shape, torch.float32, r, T)
+    assert p["tile"][1] > 0 and p["launches"] == -(-T // p["fused"])
+    yt, st = osbf.forward(x, r, T, return_sel=True)
+    with plan(0, 1):
+        y1, s1 = osbf.forward(x, r, T, return_sel=True)
+    assert torch.equal(yt, y1) and torch.equal(st, s1)
+    replay_check_planes(img[:1], yt[:1].cpu().numpy(), st[:, :1].cpu().numpy(), r, max_outliers=0)
+
+
 @pytest.mark.parametrize("dtype,tol", [(torch.float16, 2.0 ** -11 * 1.1 + 1e-5), (torch.bfloat16, 2.0 ** -8 * 1.1 + 1e-5)])
 @pytest.mark.parametrize("k", [1, 3])
 def test_reduced_precision_single_sweep(dev, dtype, tol, k):
