@@ -221,11 +221,13 @@ osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype,
 /*
  * osbf_forward_plan -- the launch plan osbf_forward uses for these arguments
  * (for profiling and tests; no device work).  Writes the output tile shape
- * (tiled kernels: tile width x height; row-streaming kernel: strip width x
- * rows per workgroup), the sweeps fused per launch (always 1 for the
- * streaming kernel) and the number of kernel launches (per chunk of at most
- * 65535 planes); ck as for osbf_forward (0 = no checkpoints).  Returns
- * OSBF_ERROR_UNSUPPORTED when no plan fits the device's LDS.
+ * (tiled kernels: tile width x height; row-streaming kernels: strip width x
+ * rows per workgroup, 0 = chosen at launch), the sweeps fused per launch (1
+ * or 2 for the streaming kernels, 2 only for the fused two-sweep kernel at
+ * r <= 5; up to 8 for the tiled kernels) and the number of sweep launches
+ * (independent of how the planes are split into grids); ck as for
+ * osbf_forward (0 = no checkpoints).  Returns OSBF_ERROR_UNSUPPORTED when no
+ * plan fits the device's LDS.
  */
 osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osbf_dtype dtype,
                               int32_t radius, int32_t iterations, int32_t ck,

@@ -125,12 +125,12 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 // Measured defaults for the compiled radii (3x2048x2048 FP32, T=30 on
 // MI355X, plan sweep over geometries, fusion depths, streaming strip widths
 // and rows per workgroup, 0 = chosen to fill the device once), in order of
-// preference: the row-streaming kernel, with two fused sweeps per launch at
-// r <= 2 (the later entries are fallbacks for devices whose LDS does not fit
-// the first).
+// preference: the row-streaming kernel, one sweep per launch (the fused
+// two-sweep kernel measured 3-4% slower at r = 1 and 2); the later entries
+// are fallbacks for devices whose LDS does not fit the first.
 struct TunedShape { int r, geom, k, rows; };
-const TunedShape kTuned[] = {{1, GEOM_S128, 2, 0}, {1, GEOM_64x48, 3, 0},
-                             {2, GEOM_S128, 2, 0}, {2, GEOM_64x48, 2, 0},
+const TunedShape kTuned[] = {{1, GEOM_S128, 1, 0}, {1, GEOM_64x48, 3, 0},
+                             {2, GEOM_S192, 1, 0}, {2, GEOM_64x48, 2, 0},
                              {3, GEOM_S128, 1, 0}, {3, GEOM_64x48, 2, 0},
                              {4, GEOM_S192, 1, 0}, {4, GEOM_64x48, 1, 0},
                              {5, GEOM_S128, 1, 0}, {5, GEOM_64x60, 1, 0},
@@ -183,6 +183,7 @@ bool tuned_plan(int planes, int H, int W, int r, int T, int dtype, Plan *out) {
     if (it == g_tune.end()) return false;
     const Plan &p = it->second;
     if (p.k > std::min(T, 8)) return false;  // fewer sweeps than the tuned fusion
+    if (stream_geom(p.geom) && !stream_width_ok(W, 4, r, std::max(p.th, stream_step(r)))) return false;
     *out = p;
     return true;
 }
@@ -223,6 +224,7 @@ Plan choose_plan_model(int planes, int H, int W, int r, int T) {
         }
         for (const auto &t : kTuned) {
             if (t.r != r) continue;
+            if (stream_geom(t.geom) && !stream_width_ok(W, 4, r, stream_step(r))) continue;
             Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
             if (stream_geom(t.geom)) p.th = t.rows;
             if (p.tw && p.lds_bytes() <= limit) return p;
@@ -232,6 +234,7 @@ Plan choose_plan_model(int planes, int H, int W, int r, int T) {
     double best_cost = 1e300;
     auto consider = [&](const Plan &p) {
         if (!p.tw || p.lds_bytes() > limit) return;
+        if (stream_geom(p.geom) && !stream_width_ok(W, 4, r, stream_step(r))) return;
         const double c = plan_cost(p, H, W, r);
         if (c < best_cost) { best_cost = c; best = p; }
     };
@@ -641,6 +644,8 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
         const int r = m.radius, step = stream_step(r);
         b.tw = ((batched_lanes() - 2 * r) / r) * r;
         b.th = (std::min(m.height, kBatchRows) + step - 1) / step * step;
+        if (!stream_width_ok(m.width, (int)elem_bytes(dtype), r, b.th))
+            return fail(OSBF_ERROR_UNSUPPORTED, "image %d: width %d too large for the batched kernel", j, m.width);
         b.rounds = m.iterations;
         L->maxr = std::max(L->maxr, r);
         const int64_t tiles = (int64_t)((m.width + b.tw - 1) / b.tw) * ((m.height + b.th - 1) / b.th);

@@ -15,12 +15,30 @@ enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 
 template <int DT> struct Storage;
 
+// Raw buffer resource over `bytes` bytes from `base`: loads and stores then
+// take a 32-bit lane offset and a scalar (row) offset, so a row walk needs no
+// 64-bit vector address arithmetic.  Word 3 is the gfx9-family format word.
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ BufRsrc buf_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Besides cvt/load/pack/round, each storage type has buffer forms: load_raw
+// returns the stored bits in an FP32 register (the value itself for F32),
+// from_raw converts them, store rounds and writes one element.
 template <> struct Storage<DT_F32> {
     using T = float;
     static __device__ __forceinline__ float cvt(T v) { return v; }
     static __device__ __forceinline__ float load(const T *p, size_t i) { return p[i]; }
     static __device__ __forceinline__ T pack(float v) { return v; }
     static __device__ __forceinline__ float round(float v) { return v; }
+    static __device__ __forceinline__ float load_raw(BufRsrc r, int voff, int soff) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ float from_raw(float v) { return v; }
+    static __device__ __forceinline__ void store(BufRsrc r, int voff, int soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+    }
 };
 
 template <> struct Storage<DT_F16> {
@@ -36,6 +54,15 @@ template <> struct Storage<DT_F16> {
         return (T)v;
     }
     static __device__ __forceinline__ float round(float v) { return (float)pack(v); }
+    static __device__ __forceinline__ float load_raw(BufRsrc r, int voff, int soff) {
+        return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ float from_raw(float v) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)__float_as_uint(v));
+    }
+    static __device__ __forceinline__ void store(BufRsrc r, int voff, int soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, pack(v)), r, voff, soff, 0);
+    }
 };
 
 template <> struct Storage<DT_BF16> {
@@ -50,6 +77,13 @@ template <> struct Storage<DT_BF16> {
     }
     static __device__ __forceinline__ float round(float v) {
         return __uint_as_float(((uint32_t)pack(v)) << 16);
+    }
+    static __device__ __forceinline__ float load_raw(BufRsrc r, int voff, int soff) {
+        return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ float from_raw(float v) { return __uint_as_float(__float_as_uint(v) << 16); }
+    static __device__ __forceinline__ void store(BufRsrc r, int voff, int soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(pack(v), r, voff, soff, 0);
     }
 };
 

@@ -38,6 +38,7 @@ hipError_t launch_forward(int dtype, const FwdLaunch &a, hipStream_t s);
 // rows (th = 0: the launch chooses th so that the chunks fill the device's
 // resident workgroup slots once).
 int stream_step(int r);                       // rows per step (th is a multiple)
+bool stream_width_ok(int W, int es, int r, int rows);  // 32-bit row offsets suffice
 size_t stream2_lds_bytes(int RW, int r);      // the fused two-sweep kernel (k = 2)
 bool stream_fusable(int RW, int r);           // whether that kernel exists for (RW, r)
 size_t stream_lds_bytes(int RW, int r);

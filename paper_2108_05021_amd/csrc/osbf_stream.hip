@@ -4,22 +4,31 @@
 
 namespace osbf {
 
-// P and V staging (CH rows each), the Q ring (CH + r rows), H (CH rows).
+// P, V and H staging (CH blocks of three rows, block stride 3 (RW + 1) + 30)
+// and the Q ring (CH + r rows of RW + 1).
 size_t stream_lds_bytes(int RW, int r) {
     const int ch = stream_step_rows(r);
-    return (size_t)(4 * ch + r) * (RW + 1) * sizeof(float);
+    return ((size_t)ch * (3 * (RW + 1) + 30) + (size_t)(ch + r) * (RW + 1)) * sizeof(float);
 }
 
-// The fused two-sweep kernel: P, V and H staging (CH rows each) and one Q
-// ring (CH + r rows) per sweep.
+// The fused two-sweep kernel: staging of both sweeps' P, their shared V and
+// H (CH rows each), one Q ring (CH + r rows) per sweep and the two edge
+// columns of the second sweep's input ring.
 size_t stream2_lds_bytes(int RW, int r) {
     const int ch = stream_step_rows(r);
-    return (size_t)(5 * ch + 2 * r) * (RW + 1) * sizeof(float);
+    return ((size_t)ch * (4 * (RW + 1) + 29) + (size_t)(2 * ch + 2 * r) * (RW + 1) + 2 * (ch + r)) * sizeof(float);
 }
 
 bool stream_fusable(int RW, int r) { return stream2_radius(r) && RW >= 5 * r; }
 
 int stream_step(int r) { return stream_step_rows(r); }
+
+// Whether a work item of `rows` rows (and its halo) of a plane W elements of
+// `es` bytes wide stays within the kernels' 32-bit row offsets.
+bool stream_width_ok(int W, int es, int r, int rows) {
+    const int ch = stream_step_rows(r);
+    return (long long)(rows + 4 * r + 2 * ch) * W * es < (1LL << 31);
+}
 
 hipError_t launch_forward_stream(int dtype, const FwdLaunch &a, hipStream_t s) {
     const bool sel = a.sel != nullptr;

@@ -38,24 +38,50 @@ constexpr int stream_step_rows(int r) {
     return r == 1 ? 2 : r == 2 ? 4 : r;
 }
 
+// Rows [row0, row1) of one plane that a work item touches, as buffer
+// resources of the iterate (and of the map): every access is a 32-bit lane
+// offset plus a scalar row offset from row0.
+struct ItemRows {
+    BufRsrc src, dst, sel;
+    int row0, H, W;
+    int es;  // bytes per element of the iterate
+    __device__ __forceinline__ int ld_off(int y) const { return (clampi(y, 0, H - 1) - row0) * W * es; }
+    __device__ __forceinline__ int st_off(int y) const { return (y - row0) * W * es; }
+    __device__ __forceinline__ int sel_off(int y) const { return (y - row0) * W; }
+};
+
 // MODE: MODE_EXACT, MODE_FAST (quadrant means only, no H field) or MODE_BOX,
 // as in the tiled kernels; maps (SEL) only with MODE_EXACT.
 // One work item t = (plane * chunks + chunk) * strips + strip: rows
 // [chunk * th, chunk * th + th) of one strip of one plane (shared by the
 // single-image and the batched kernels).
+//
+// Registers: the lane's P and V rows [s - R, s + CH) sit in two rings of
+// L = R + CH registers whose origin advances by CH rows per step, so the step
+// body is unrolled over the ring period NRB = CH / R + 1 and every ring slot,
+// every slot of the Q ring in LDS and every LDS offset is a compile-time
+// constant.  The next step's rows are loaded straight into the ring slots of
+// the rows [s - R, s - R + CH) once those are staged in LDS (the evaluation
+// reads c from LDS).  Lanes outside the image hold the clamped column, so the
+// row sums read the replicate extension without clamping indices.
 template <int DT, int R, int RW, int CH, bool SEL, int MODE>
-__device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) {
+__device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float *lds) {
     using S = Storage<DT>;
     using T = typename S::T;
     static_assert(CH % R == 0, "a step is whole blocks of R rows");
     static_assert(RW % 64 == 0 && RW >= 2 * R + R, "region width");
     constexpr int M = CH / R;        // blocks per step
-    constexpr int NRB = M + 1;       // blocks in the Q/H ring
+    constexpr int NRB = M + 1;       // ring period in steps; Q ring of NRB * R = L rows
+    constexpr int L = R + CH;        // register ring length
     constexpr int PITCH = RW + 1;
-    float *const Pl = lds;                      // CH rows: P of the rows evaluated this step
-    float *const Vl = lds + CH * PITCH;         // CH rows: V of the step's new rows
-    float *const Qr = lds + 2 * CH * PITCH;     // NRB * R rows: ring of Q
-    float *const Hr = Qr + NRB * R * PITCH;     // CH rows: H of the rows evaluated this step
+    // staging, CH blocks of three rows: P of the i-th row evaluated this step
+    // (row s - R + i), V of the step's i-th new row (row s + i), H of the
+    // i-th evaluated row; then the ring of Q (L rows).  Block stride = 1 mod
+    // 32 banks, as the ring's pitch, so that the row-sum items (consecutive
+    // lanes = consecutive rows of one block of columns) hit distinct banks.
+    constexpr int RS = 3 * PITCH + 30;
+    float *const Sg = lds;
+    float *const Qr = lds + CH * RS;
 
     const int lx = threadIdx.x;
     const int H = a.H, W = a.W, TW = a.tw, YC = a.th;
@@ -66,23 +92,34 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
     const int ox = X0 - R;
     const int xa = X0, xb = min(W, X0 + TW), xend = xb + R;
     const int yb = min(H, Y0 + YC), yend = yb + R;
-    const int lo = max(0, xa - R), hi = min(W, xend) - 1;  // columns the row sums read
     const int x = ox + lx;
     const bool own = x >= xa && x < xb;
-    const size_t plane_off = (size_t)plane * H * W;
-    // lanes outside the image read a clamped column; their LDS columns are
-    // never read (the row sums clamp to [lo, hi])
-    const T *src = (const T *)a.src + plane_off + min(max(x, 0), W - 1);
-    T *dst = (T *)a.dst + plane_off;
-    uint8_t *sel = SEL ? a.sel + plane_off : nullptr;
+    const int nsteps = (yend - Y0 + CH - 1) / CH;
+
+    ItemRows io;
+    io.H = H;
+    io.W = W;
+    io.es = (int)sizeof(T);
+    io.row0 = max(0, Y0 - R);
+    {
+        const int row1 = min(H, Y0 + nsteps * CH);  // past the last row loaded or stored
+        const size_t first = (size_t)plane * H * W + (size_t)io.row0 * W;
+        const uint32_t n = (uint32_t)(row1 - io.row0) * (uint32_t)W;
+        io.src = buf_rsrc((const T *)a.src + first, n * sizeof(T));
+        io.dst = buf_rsrc((T *)a.dst + first, n * sizeof(T));
+        io.sel = SEL ? buf_rsrc(a.sel + first, n) : io.dst;
+    }
+    const int vld = clampi(x, 0, W - 1) * (int)sizeof(T);  // this lane's column (clamped)
+    const int vst = x * (int)sizeof(T);
 
     // This lane's row-sum work items, the same in every step: items of one
     // block of R rows are consecutive, row fastest, so 32 consecutive lanes
     // read 32 distinct banks (row pitch = 1 mod 32, column blocks R apart)
     // when R divides 32.  CH * nb <= M * RW, so a lane has at most M items.
+    // ib: the item's first LDS column in its row, relative to the row start.
     const int nb = (xend - xa + R - 1) / R;
-    int it_row[M], it_x0[M];
-    bool it_ok[M], it_fast[M];
+    int it_row[M], it_ib[M];
+    bool it_ok[M], it_full[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int it = lx + k * RW;
@@ -90,8 +127,9 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
         const int b = rem / R;
         it_ok[k] = it < CH * nb;
         it_row[k] = m * R + (rem - b * R);
-        it_x0[k] = xa + b * R;
-        it_fast[k] = it_x0[k] - R >= lo && it_x0[k] + R - 1 <= hi;  // no column clamped
+        const int x0 = xa + b * R;
+        it_ib[k] = x0 - R - ox;
+        it_full[k] = x0 + R <= xend;
     }
 
     constexpr float fr1 = (float)(R + 1), f2r1 = (float)(2 * R + 1);
@@ -99,96 +137,107 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
     const float invN = 1.0f / N;
     const float inv_box = 1.0f / (f2r1 * f2r1);
 
-    float pr[CH + R], vr[CH + R];
-    T raw[CH];  // input rows of the next step
+    float PR[L], VR[L];  // physical rings
 #pragma unroll
-    for (int i = 0; i < R; ++i) pr[i] = S::cvt(src[(size_t)min(max(Y0 - R + i, 0), H - 1) * W]);
+    for (int j = 0; j < R; ++j) {
+        PR[j] = S::from_raw(S::load_raw(io.src, vld, io.ld_off(Y0 - R + j)));
+        VR[j] = 0.f;  // rows above Y0: never evaluated
+    }
 #pragma unroll
-    for (int i = 0; i < R; ++i) vr[i] = 0.f;  // rows above Y0: never evaluated
-    auto load_step = [&](int s) {
-#pragma unroll
-        for (int i = 0; i < CH; ++i) raw[i] = src[(size_t)min(max(s + i, 0), H - 1) * W];
-    };
+    for (int j = 0; j < CH; ++j) PR[R + j] = S::load_raw(io.src, vld, io.ld_off(Y0 + j));
 
-    const int nsteps = (yend - Y0 + CH - 1) / CH;
     float out_v[CH];
     int out_i[CH];
     int out_s = 0;
     bool pending = false;
-    int base = 0;  // ring block of rows [s - R, s): (n * M) mod NRB
+    const int rowb = W * (int)sizeof(T);
     auto store_step = [&]() {
         auto put = [&](int i) {
-            const size_t o = (size_t)(out_s - R + i) * W + x;
-            dst[o] = S::pack(out_v[i]);
-            if (SEL) sel[o] = (uint8_t)out_i[i];
+            const int y = out_s - R + i;
+            S::store(io.dst, vst, io.st_off(y), out_v[i]);
+            if (SEL) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)out_i[i], io.sel, x, io.sel_off(y), 0);
         };
-        if (out_s - R >= Y0 && out_s - R + CH <= yb) {
+        if (out_s - R >= Y0 && out_s - R + CH <= yb) {  // uniform: offsets step by a row
+            int o = io.st_off(out_s - R), os = io.sel_off(out_s - R);
 #pragma unroll
-            for (int i = 0; i < CH; ++i) put(i);
+            for (int i = 0; i < CH; ++i, o += rowb, os += W) {
+                S::store(io.dst, vst, o, out_v[i]);
+                if (SEL) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)out_i[i], io.sel, x, os, 0);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < CH; ++i)
                 if (out_s - R + i >= Y0 && out_s - R + i < yb) put(i);
         }
     };
-    load_step(Y0);
-    for (int n = 0; n < nsteps; ++n) {
+
+    auto step = [&](auto ph, int n) {
+        constexpr int PH = decltype(ph)::value;
+        // physical slot of logical ring row j (row s - R + j)
+        auto sl = [](int j) { return (j + PH * CH) % L; };
+        // Q ring row of image row s + j, j in [-R, CH)
+        auto qrow = [](int j) { return (PH * CH + R + j) % L; };
         const int s = Y0 + n * CH;
-        // V of rows [s, s + CH) from input rows [s - R, s + CH), in registers
+        // V of rows [s, s + CH) from P rows [s - R, s + CH), in registers
 #pragma unroll
-        for (int i = 0; i < CH; ++i) pr[R + i] = S::cvt(raw[i]);
+        for (int j = R; j < L; ++j) PR[sl(j)] = S::from_raw(PR[sl(j)]);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const float *p = pr + m * R;
-            float v = p[0];
+            float v = PR[sl(m * R)];
 #pragma unroll
-            for (int tt = 1; tt <= R; ++tt) v += p[tt];
-            vr[R + m * R] = v;
+            for (int tt = 1; tt <= R; ++tt) v += PR[sl(m * R + tt)];
+            VR[sl(R + m * R)] = v;
 #pragma unroll
             for (int tt = 1; tt < R; ++tt) {
-                v += p[R + tt] - p[tt - 1];
-                vr[R + m * R + tt] = v;
+                v += PR[sl(R + m * R + tt)] - PR[sl(m * R + tt - 1)];
+                VR[sl(R + m * R + tt)] = v;
             }
         }
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            Pl[i * PITCH + lx] = pr[i];  // rows [s - R, s - R + CH), evaluated this step
-            Vl[i * PITCH + lx] = vr[R + i];
+            Sg[i * RS + lx] = PR[sl(i)];  // rows [s - R, s - R + CH), evaluated this step
+            Sg[i * RS + PITCH + lx] = VR[sl(R + i)];
         }
-        // the previous step's results, then the next step's loads
+        // the previous step's results, then the next step's loads into the
+        // slots of the rows just staged
         if (pending && own) store_step();
-        if (n + 1 < nsteps) load_step(s + CH);
+        if (n + 1 < nsteps) {
+            if (s + 2 * CH <= H) {  // uniform: no clamped row, offsets step by a row
+                int o = io.ld_off(s + CH);
+#pragma unroll
+                for (int i = 0; i < CH; ++i, o += rowb) PR[sl(i)] = S::load_raw(io.src, vld, o);
+            } else {
+#pragma unroll
+                for (int i = 0; i < CH; ++i) PR[sl(i)] = S::load_raw(io.src, vld, io.ld_off(s + CH + i));
+            }
+        }
         __syncthreads();
 
-        // Q of rows [s, s + CH) ∩ [Y0, yend) into ring blocks base + 1 ..
-        // base + M, and H of the rows evaluated this step, [s - R, s - R +
-        // CH), into Hr; columns [xa, xend).  (An evaluated row y < yb has
-        // y + R = s + i < yend, so its item is never skipped.)
+        // Q of rows [s, s + CH) ∩ [Y0, yend) into the ring and H of the rows
+        // evaluated this step, [s - R, s - R + CH), into Hr; columns [xa, xend).
+        // (An evaluated row y < yb has y + R = s + i < yend, so its item is
+        // never skipped.)
 #pragma unroll
         for (int k = 0; k < M; ++k) {
-            const int i = it_row[k], x0 = it_x0[k];
+            const int i = it_row[k];
             if (it_ok[k] && s + i < yend) {
-                const float *vrow = Vl + i * PITCH - ox;  // + image column
-                const float *prow = Pl + i * PITCH - ox;
+                const int ib = i * RS + it_ib[k];
                 float v[2 * R], p[2 * R];
-                if (it_fast[k]) {  // immediate offsets
 #pragma unroll
-                    for (int tt = 0; tt < 2 * R; ++tt) {
-                        v[tt] = vrow[x0 - R + tt];
-                        p[tt] = prow[x0 - R + tt];
-                    }
-                } else {
-#pragma unroll
-                    for (int tt = 0; tt < 2 * R; ++tt) {
-                        const int col = min(max(x0 - R + tt, lo), hi);
-                        v[tt] = vrow[col];
-                        p[tt] = prow[col];
-                    }
+                for (int tt = 0; tt < 2 * R; ++tt) {
+                    p[tt] = Sg[ib + tt];
+                    v[tt] = Sg[ib + PITCH + tt];
                 }
-                int blk = base + 1 + i / R;
-                blk = blk >= NRB ? blk - NRB : blk;
-                const int ro = (blk * R + i % R) * PITCH - ox;
-                float *qrow = Qr + ro, *hrow = Hr + i * PITCH - ox;
+                int qo;
+                if constexpr (M == 1) {
+                    qo = qrow(0) * PITCH + it_ib[k] + R;  // i < R: no wrap
+                    qo += i * PITCH;
+                } else {
+                    const int qr = (PH * CH + R) % L + i;
+                    qo = (qr >= L ? qr - L : qr) * PITCH + it_ib[k] + R;
+                }
+                float *qrow_p = Qr + qo;
+                float *hrow_p = Sg + ib + 2 * PITCH + R;
                 constexpr bool HF = MODE != MODE_FAST;  // the fast mode needs no H
                 float q = v[0], h = p[0];
 #pragma unroll
@@ -196,27 +245,28 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
                     q += v[tt];
                     if (HF) h += p[tt];
                 }
-                qrow[x0] = q;
-                if (HF) hrow[x0] = h;
-                if (x0 + R <= xend) {
+                qrow_p[0] = q;
+                if (HF) hrow_p[0] = h;
+                if (it_full[k]) {
 #pragma unroll
                     for (int tt = 1; tt < R; ++tt) {
                         q += v[R + tt] - v[tt - 1];
-                        qrow[x0 + tt] = q;
+                        qrow_p[tt] = q;
                         if (HF) {
                             h += p[R + tt] - p[tt - 1];
-                            hrow[x0 + tt] = h;
+                            hrow_p[tt] = h;
                         }
                     }
                 } else {
+                    const int x0 = it_ib[k] + R + ox;
 #pragma unroll
                     for (int tt = 1; tt < R; ++tt) {
                         if (x0 + tt < xend) {
                             q += v[R + tt] - v[tt - 1];
-                            qrow[x0 + tt] = q;
+                            qrow_p[tt] = q;
                             if (HF) {
                                 h += p[R + tt] - p[tt - 1];
-                                hrow[x0 + tt] = h;
+                                hrow_p[tt] = h;
                             }
                         }
                     }
@@ -227,74 +277,74 @@ __device__ __forceinline__ void fwd_stream_item(FwdLaunch a, int t, float *lds) 
 
         // selection and update of rows [s - R, s + CH - R) ∩ [Y0, yb)
         if (own) {
-            auto eval_row = [&](int i) {
-                int bu = base + i / R;
-                bu = bu >= NRB ? bu - NRB : bu;
-                const int bd = bu + 1 >= NRB ? bu + 1 - NRB : bu + 1;
-                const int ou = (bu * R + i % R) * PITCH + lx;
-                const int od = (bd * R + i % R) * PITCH + lx;
-                const int oh = i * PITCH + lx;
-                const float c = pr[i];
-                const float nw = Qr[ou], ne = Qr[ou + R], sw = Qr[od], se = Qr[od + R];
+            auto eval_row = [&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int ou = qrow(i - R) * PITCH, od = qrow(i) * PITCH, op = i * RS, oh = op + 2 * PITCH;
+                const float c = Sg[op + lx];
+                const float nw = Qr[ou + lx], ne = Qr[ou + lx + R], sw = Qr[od + lx], se = Qr[od + lx + R];
+                const float vu = VR[sl(i)], vd = VR[sl(i + R)];
                 if constexpr (MODE == MODE_BOX) {
-                    out_v[i] = S::round(box_sum(nw, ne, sw, se, Hr[oh], Hr[oh + R], vr[i], vr[i + R], c) * inv_box);
+                    out_v[i] = S::round(box_sum(nw, ne, sw, se, Sg[oh + lx], Sg[oh + lx + R], vu, vd, c) * inv_box);
                     out_i[i] = 0;
                 } else {
                     float d[8];
                     if constexpr (MODE == MODE_FAST)
                         fast_distances(d, nw, ne, sw, se, c, fr1);
                     else
-                        exact_distances(d, nw, ne, sw, se, Hr[oh], Hr[oh + R], vr[i], vr[i + R], c, fr1, f2r1, N);
+                        exact_distances(d, nw, ne, sw, se, Sg[oh + lx], Sg[oh + lx + R], vu, vd, c, fr1, f2r1, N);
                     const Pick pk = select8<SEL>(d);
                     out_v[i] = S::round(fmaf(pk.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c));
                     out_i[i] = pk.idx;
                 }
             };
             if (s - R >= Y0 && s - R + CH <= yb) {  // uniform over the workgroup
-#pragma unroll
-                for (int i = 0; i < CH; ++i) eval_row(i);
+                static_for<0, CH>([&](auto ic) { eval_row(ic); });
             } else {
-#pragma unroll
-                for (int i = 0; i < CH; ++i)
-                    if (s - R + i >= Y0 && s - R + i < yb) eval_row(i);
+                static_for<0, CH>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    if (s - R + i >= Y0 && s - R + i < yb) eval_row(ic);
+                });
             }
         }
         out_s = s;
         pending = true;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            pr[i] = pr[CH + i];
-            vr[i] = vr[CH + i];
-        }
-        base = base == 0 ? M : base - 1;
+    };
+
+    for (int n = 0; n < nsteps; n += NRB) {
+        static_for<0, NRB>([&](auto ph) {
+            if (n + decltype(ph)::value < nsteps) step(ph, n + decltype(ph)::value);
+        });
     }
     if (pending && own) store_step();
 }
 
 // Two fused sweeps on one work item (small radii): stage A runs the first
 // sweep on the strip grown by R on each side (rows grown by R), reading the
-// input from global memory; its rounded results, still in the lane's
-// registers, are stage B's new input rows, from which stage B runs the
+// input from global memory; its rounded results are written straight into
+// stage B's register ring as B's new input rows, from which stage B runs the
 // second sweep on the strip itself.  Rows stage B needs above row 0 or below
-// row H-1 are replicated from those rows (the clamp), so stage B sees
-// exactly the clamp extension of the first sweep's output.  The P and V
-// staging and the H rows are shared (stage B's phases follow stage A's after
-// barriers), each stage keeps its own Q ring: LDS (5 CH + 2R) rows, four
-// barriers per step of CH rows of both sweeps.  The region is TW + 4R
-// columns wide.  Every block and column anchor is a multiple of R, so the
-// results are those of two single-sweep launches, bit for bit.
+// row H-1 are replicated from those rows (the clamp), so stage B sees exactly
+// the clamp extension of the first sweep's output.  The region is TW + 4R
+// columns wide; four barriers per step of CH rows of both sweeps (five in
+// strips at an image edge).  LDS: CH blocks of four rows (A's P, the V rows
+// both stages share, B's P, the H rows both share: A's evaluation may still
+// read its P while B stages its own), one Q ring of L rows per stage and 2L
+// floats for the edge columns.  Registers and LDS offsets follow
+// the single-sweep item (rings unrolled over their period).  Every block and
+// column anchor is a multiple of R, so the results are those of two
+// single-sweep launches, bit for bit.
 template <int DT, int R, int RW, int CH, bool SEL, int MODE>
 __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, float *lds) {
     using S = Storage<DT>;
     using T = typename S::T;
     static_assert(CH % R == 0, "a step is whole blocks of R rows");
     static_assert(RW % 64 == 0 && RW >= 5 * R, "region width");
-    constexpr int M = CH / R, NRB = M + 1, PITCH = RW + 1;
-    float *const Pl = lds;                          // CH rows
-    float *const Vl = lds + CH * PITCH;             // CH rows
-    float *const Hr = lds + 2 * CH * PITCH;         // CH rows
-    float *const QA = lds + 3 * CH * PITCH;         // NRB * R rows (stage A ring)
-    float *const QB = QA + NRB * R * PITCH;         // NRB * R rows (stage B ring)
+    constexpr int M = CH / R, NRB = M + 1, L = R + CH, PITCH = RW + 1;
+    constexpr int RS = 4 * PITCH + 29;      // staging block: PA, V, PB, H rows (stride 1 mod 32)
+    float *const Sg = lds;
+    float *const QA = lds + CH * RS;        // L rows (stage A ring)
+    float *const QB = QA + L * PITCH;       // L rows (stage B ring)
+    float *const Ex = QB + L * PITCH;       // 2L: ring rows of columns 0 and W - 1
 
     const int lx = threadIdx.x;
     const int H = a.H, W = a.W, TW = a.tw, YC = a.th;
@@ -305,19 +355,13 @@ __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, floa
     const int yb = min(H, Y0 + YC);
     const int ox = X0 - 2 * R;  // image column of region column 0
     const int x = ox + lx;
-    const size_t plane_off = (size_t)plane * H * W;
-    const T *src = (const T *)a.src + plane_off + min(max(x, 0), W - 1);
-    T *dst = (T *)a.dst + plane_off;
-    uint8_t *selA = SEL ? a.sel + plane_off : nullptr;
-    uint8_t *selB = SEL ? a.sel + a.sel_stride + plane_off : nullptr;
 
     // stage geometry: evaluated columns [xa, xb) and rows [ya, ye), fields
-    // on columns [xa, xend) and rows up to yend, row sums reading [lo, hi]
-    struct Geo { int xa, xb, xend, lo, hi, ya, ye, yend, nb; };
+    // on columns [xa, xend) and rows up to yend
+    struct Geo { int xa, xb, xend, ya, ye, yend, nb; };
     auto geo = [&](int xa, int xb, int ya, int ye) {
         Geo g;
         g.xa = xa; g.xb = xb; g.xend = xb + R;
-        g.lo = max(0, xa - R); g.hi = min(W, g.xend) - 1;
         g.ya = ya; g.ye = ye; g.yend = ye + R;
         g.nb = (g.xend - xa + R - 1) / R;
         return g;
@@ -325,10 +369,33 @@ __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, floa
     const Geo gA = geo(max(0, X0 - R), min(W, X0 + TW + R), max(0, Y0 - R), min(H, yb + R));
     const Geo gB = geo(X0, min(W, X0 + TW), Y0, yb);
     const bool ownA = x >= gA.xa && x < gA.xb, ownB = x >= gB.xa && x < gB.xb;
-    const bool coreA = x >= X0 && x < X0 + TW;  // stage A writes maps only here
+    const int nsteps = (yb + 2 * R - gA.ya + CH - 1) / CH;
 
-    // each stage's row-sum items, the same every step (as fwd_stream_item)
-    struct Items { int row[M], x0[M]; bool ok[M], fast[M]; };
+    ItemRows io;
+    io.H = H;
+    io.W = W;
+    io.es = (int)sizeof(T);
+    io.row0 = max(0, gA.ya - R);
+    {
+        const int row1 = min(H, gA.ya + nsteps * CH);  // past the last row loaded or stored
+        const size_t first = (size_t)plane * H * W + (size_t)io.row0 * W;
+        const uint32_t n = (uint32_t)(row1 - io.row0) * (uint32_t)W;
+        io.src = buf_rsrc((const T *)a.src + first, n * sizeof(T));
+        io.dst = buf_rsrc((T *)a.dst + first, n * sizeof(T));
+        io.sel = SEL ? buf_rsrc(a.sel + first, n) : io.dst;
+    }
+    BufRsrc selB = io.sel;
+    if (SEL) {
+        const size_t first = (size_t)plane * H * W + (size_t)io.row0 * W;
+        const uint32_t n = (uint32_t)(min(H, gA.ya + nsteps * CH) - io.row0) * (uint32_t)W;
+        selB = buf_rsrc(a.sel + a.sel_stride + first, n);
+    }
+    const int vld = clampi(x, 0, W - 1) * (int)sizeof(T);
+    const int vst = x * (int)sizeof(T);
+
+    // each stage's row-sum items, the same every step (as fwd_stream_item);
+    // ib: the item's first LDS column relative to its row
+    struct Items { int row[M], ib[M]; bool ok[M], full[M]; };
     auto items = [&](const Geo &g) {
         Items it;
 #pragma unroll
@@ -338,8 +405,9 @@ __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, floa
             const int b = rem / R;
             it.ok[k] = i < CH * g.nb;
             it.row[k] = m * R + (rem - b * R);
-            it.x0[k] = g.xa + b * R;
-            it.fast[k] = it.x0[k] - R >= g.lo && it.x0[k] + R - 1 <= g.hi;
+            const int x0 = g.xa + b * R;
+            it.ib[k] = x0 - R - ox;
+            it.full[k] = x0 + R <= g.xend;
         }
         return it;
     };
@@ -350,70 +418,84 @@ __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, floa
     const float invN = 1.0f / N;
     const float inv_box = 1.0f / (f2r1 * f2r1);
 
-    float prA[CH + R], vrA[CH + R], prB[CH + R], vrB[CH + R];
-    float outA[CH], outB[CH];
-    int idxA[CH], idxB[CH];
-    T raw[CH];
+    float PA[L], VA[L], PB[L], VB[L];  // physical rings of both stages
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        prA[i] = S::cvt(src[(size_t)min(max(gA.ya - R + i, 0), H - 1) * W]);
-        vrA[i] = prB[i] = vrB[i] = 0.f;
+    for (int j = 0; j < R; ++j) {
+        PA[j] = S::from_raw(S::load_raw(io.src, vld, io.ld_off(gA.ya - R + j)));
+        VA[j] = PB[j] = VB[j] = 0.f;
     }
 #pragma unroll
-    for (int i = 0; i < CH; ++i) outA[i] = outB[i] = 0.f;
-    auto load_step = [&](int s0) {
+    for (int j = 0; j < CH; ++j) {
+        PA[R + j] = S::load_raw(io.src, vld, io.ld_off(gA.ya + j));
+        PB[R + j] = 0.f;
+    }
+    float outB[CH];
+    int idxA[CH], idxB[CH];
+    float hold = 0.f;  // stage A's row H - 1 (bottom chunks)
+    int outB_s = 0;
+    bool pending = false;
+    const int rowb = W * (int)sizeof(T);
+    auto store_prev = [&]() {
+        if (!SEL && outB_s - R >= Y0 && outB_s - R + CH <= yb) {  // uniform: offsets step by a row
+            int o = io.st_off(outB_s - R);
 #pragma unroll
-        for (int i = 0; i < CH; ++i) raw[i] = src[(size_t)min(max(s0 + i, 0), H - 1) * W];
+            for (int i = 0; i < CH; ++i, o += rowb) S::store(io.dst, vst, o, outB[i]);
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int y = outB_s - R + i;  // stage B's rows of the previous step
+            if (y >= Y0 && y < yb) {
+                S::store(io.dst, vst, io.st_off(y), outB[i]);
+                if (SEL) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)idxB[i], selB, x, io.sel_off(y), 0);
+            }
+            const int ya = outB_s + i;  // stage A's rows of the previous step
+            if (SEL && ya >= Y0 && ya < yb)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)idxA[i], io.sel, x, io.sel_off(ya), 0);
+        }
     };
 
-    // V of the step's new rows in registers; P of the rows evaluated this step
-    // and the new V rows to LDS
-    auto v_phase = [&](float *pr, float *vr) {
+    // V of the step's new rows into the ring, P of the rows evaluated this
+    // step and the new V rows to LDS (P at staging row `prow` of each block)
+    auto v_phase = [&](auto ph, float *P, float *V, int prow) {
+        constexpr int PH = decltype(ph)::value;
+        auto sl = [](int j) { return (j + PH * CH) % L; };
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const float *p = pr + m * R;
-            float v = p[0];
+            float v = P[sl(m * R)];
 #pragma unroll
-            for (int tt = 1; tt <= R; ++tt) v += p[tt];
-            vr[R + m * R] = v;
+            for (int tt = 1; tt <= R; ++tt) v += P[sl(m * R + tt)];
+            V[sl(R + m * R)] = v;
 #pragma unroll
             for (int tt = 1; tt < R; ++tt) {
-                v += p[R + tt] - p[tt - 1];
-                vr[R + m * R + tt] = v;
+                v += P[sl(R + m * R + tt)] - P[sl(m * R + tt - 1)];
+                V[sl(R + m * R + tt)] = v;
             }
         }
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            Pl[i * PITCH + lx] = pr[i];
-            Vl[i * PITCH + lx] = vr[R + i];
+            Sg[i * RS + prow * PITCH + lx] = P[sl(i)];
+            Sg[i * RS + PITCH + lx] = V[sl(R + i)];
         }
     };
-    // Q of rows [s, s + CH) into the ring, H of rows [s - R, s - R + CH)
-    auto qh_phase = [&](const Geo &g, const Items &it, int s0, int base, float *Q) {
+    // Q of rows [s, s + CH) into the ring, H of rows [s - R, s - R + CH);
+    // the item reads P at staging row prow and V at row 1 of each block
+    auto qh_phase = [&](auto ph, const Geo &g, const Items &it, int s0, float *Q, int prow) {
+        constexpr int PH = decltype(ph)::value;
 #pragma unroll
         for (int k = 0; k < M; ++k) {
-            const int i = it.row[k], x0 = it.x0[k];
+            const int i = it.row[k];
             if (!it.ok[k] || s0 + i >= g.yend) continue;
-            const float *vrow = Vl + i * PITCH - ox;  // + image column
-            const float *prow = Pl + i * PITCH - ox;
+            const int ib = i * RS + it.ib[k];
             float v[2 * R], p[2 * R];
-            if (it.fast[k]) {
 #pragma unroll
-                for (int tt = 0; tt < 2 * R; ++tt) {
-                    v[tt] = vrow[x0 - R + tt];
-                    p[tt] = prow[x0 - R + tt];
-                }
-            } else {
-#pragma unroll
-                for (int tt = 0; tt < 2 * R; ++tt) {
-                    const int col = min(max(x0 - R + tt, g.lo), g.hi);
-                    v[tt] = vrow[col];
-                    p[tt] = prow[col];
-                }
+            for (int tt = 0; tt < 2 * R; ++tt) {
+                p[tt] = Sg[ib + prow * PITCH + tt];
+                v[tt] = Sg[ib + PITCH + tt];
             }
-            int blk = base + 1 + i / R;
-            blk = blk >= NRB ? blk - NRB : blk;
-            float *qrow = Q + (blk * R + i % R) * PITCH - ox, *hrow = Hr + i * PITCH - ox;
+            const int qr = (PH * CH + R) % L + i;
+            float *qrow_p = Q + (qr >= L ? qr - L : qr) * PITCH + it.ib[k] + R;
+            float *hrow_p = Sg + ib + 3 * PITCH + R;
             constexpr bool HF = MODE != MODE_FAST;
             float q = v[0], h = p[0];
 #pragma unroll
@@ -421,132 +503,134 @@ __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, floa
                 q += v[tt];
                 if (HF) h += p[tt];
             }
-            qrow[x0] = q;
-            if (HF) hrow[x0] = h;
+            qrow_p[0] = q;
+            if (HF) hrow_p[0] = h;
+            if (it.full[k]) {
 #pragma unroll
-            for (int tt = 1; tt < R; ++tt) {
-                if (x0 + tt < g.xend) {
+                for (int tt = 1; tt < R; ++tt) {
                     q += v[R + tt] - v[tt - 1];
-                    qrow[x0 + tt] = q;
+                    qrow_p[tt] = q;
                     if (HF) {
                         h += p[R + tt] - p[tt - 1];
-                        hrow[x0 + tt] = h;
+                        hrow_p[tt] = h;
+                    }
+                }
+            } else {
+                const int x0 = it.ib[k] + R + ox;
+#pragma unroll
+                for (int tt = 1; tt < R; ++tt) {
+                    if (x0 + tt < g.xend) {
+                        q += v[R + tt] - v[tt - 1];
+                        qrow_p[tt] = q;
+                        if (HF) {
+                            h += p[R + tt] - p[tt - 1];
+                            hrow_p[tt] = h;
+                        }
                     }
                 }
             }
         }
     };
-    // rows [s - R, s - R + CH) ∩ [ya, ye) of this lane's column
-    auto eval_phase = [&](const Geo &g, int s0, int base, const float *Q, const float *pr, const float *vr,
-                          float *out, int *idx) {
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
+    // rows [s - R, s - R + CH) ∩ [ya, ye) of this lane's column; fn(i, value,
+    // index) with i an integral constant
+    auto eval_phase = [&](auto ph, const Geo &g, int s0, const float *Q, const float *V, int prow, auto &&fn) {
+        constexpr int PH = decltype(ph)::value;
+        auto sl = [](int j) { return (j + PH * CH) % L; };
+        auto qrow = [](int j) { return (PH * CH + R + j) % L; };
+        static_for<0, CH>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
             const int y = s0 - R + i;
-            if (y < g.ya || y >= g.ye) continue;  // uniform over the workgroup
-            int bu = base + i / R;
-            bu = bu >= NRB ? bu - NRB : bu;
-            const int bd = bu + 1 >= NRB ? bu + 1 - NRB : bu + 1;
-            const int ou = (bu * R + i % R) * PITCH + lx;
-            const int od = (bd * R + i % R) * PITCH + lx;
-            const int oh = i * PITCH + lx;
-            const float c = pr[i];
-            const float nw = Q[ou], ne = Q[ou + R], sw = Q[od], se = Q[od + R];
+            if (y < g.ya || y >= g.ye) return;  // uniform over the workgroup
+            constexpr int ou = qrow(i - R) * PITCH, od = qrow(i) * PITCH;
+            const int op = i * RS + prow * PITCH, oh = i * RS + 3 * PITCH;
+            const float c = Sg[op + lx];
+            const float nw = Q[ou + lx], ne = Q[ou + lx + R], sw = Q[od + lx], se = Q[od + lx + R];
+            const float vu = V[sl(i)], vd = V[sl(i + R)];
             if constexpr (MODE == MODE_BOX) {
-                out[i] = S::round(box_sum(nw, ne, sw, se, Hr[oh], Hr[oh + R], vr[i], vr[i + R], c) * inv_box);
-                idx[i] = 0;
+                fn(ic, S::round(box_sum(nw, ne, sw, se, Sg[oh + lx], Sg[oh + lx + R], vu, vd, c) * inv_box), 0);
             } else {
                 float d[8];
                 if constexpr (MODE == MODE_FAST)
                     fast_distances(d, nw, ne, sw, se, c, fr1);
                 else
-                    exact_distances(d, nw, ne, sw, se, Hr[oh], Hr[oh + R], vr[i], vr[i + R], c, fr1, f2r1, N);
+                    exact_distances(d, nw, ne, sw, se, Sg[oh + lx], Sg[oh + lx + R], vu, vd, c, fr1, f2r1, N);
                 const Pick pk = select8<SEL>(d);
-                out[i] = S::round(fmaf(pk.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c));
-                idx[i] = pk.idx;
+                fn(ic, S::round(fmaf(pk.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c)), pk.idx);
             }
-        }
+        });
     };
 
-    const int nsteps = (yb + 2 * R - gA.ya + CH - 1) / CH;
-    int baseA = 0, baseB = 0, outB_s = 0;
-    bool pending = false;
-    auto store_B = [&]() {
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int y = outB_s - R + i;
-            if (y >= Y0 && y < yb) {
-                const size_t o = (size_t)y * W + x;
-                dst[o] = S::pack(outB[i]);
-                if (SEL) selB[o] = (uint8_t)idxB[i];
-            }
-        }
-    };
-    load_step(gA.ya);
-    for (int n = 0; n < nsteps; ++n) {
+    auto step = [&](auto ph, int n) {
+        constexpr int PH = decltype(ph)::value;
+        auto sl = [](int j) { return (j + PH * CH) % L; };
         const int sA = gA.ya + n * CH, sB = sA - R;
         // stage A: the first sweep from the input
 #pragma unroll
-        for (int i = 0; i < CH; ++i) prA[R + i] = S::cvt(raw[i]);
-        v_phase(prA, vrA);
-        if (pending && ownB) store_B();
-        if (n + 1 < nsteps) load_step(sA + CH);
+        for (int j = R; j < L; ++j) PA[sl(j)] = S::from_raw(PA[sl(j)]);
+        v_phase(ph, PA, VA, 0);
+        if (pending && ownB) store_prev();
+        if (n + 1 < nsteps) {
+            if (sA + CH >= 0 && sA + 2 * CH <= H) {  // uniform: no clamped row
+                int o = io.ld_off(sA + CH);
+#pragma unroll
+                for (int i = 0; i < CH; ++i, o += rowb) PA[sl(i)] = S::load_raw(io.src, vld, o);
+            } else {
+#pragma unroll
+                for (int i = 0; i < CH; ++i) PA[sl(i)] = S::load_raw(io.src, vld, io.ld_off(sA + CH + i));
+            }
+        }
         __syncthreads();
-        qh_phase(gA, iA, sA, baseA, QA);
+        qh_phase(ph, gA, iA, sA, QA, 0);
         __syncthreads();
+        // stage A's results are stage B's new rows [sB, sB + CH) (logical
+        // ring rows j <-> image rows sB - R + j); rows stage B reads above
+        // row 0 repeat row 0 (set when row 0 is produced: they are the ring
+        // rows below it then), rows below row H - 1 repeat row H - 1
         if (ownA) {
-            eval_phase(gA, sA, baseA, QA, prA, vrA, outA, idxA);
-            if (SEL && coreA) {
-#pragma unroll
-                for (int i = 0; i < CH; ++i) {
-                    const int y = sA - R + i;
-                    if (y >= Y0 && y < yb) selA[(size_t)y * W + x] = (uint8_t)idxA[i];
-                }
-            }
+            eval_phase(ph, gA, sA, QA, VA, 0, [&](auto ic, float u, int m) {
+                constexpr int i = decltype(ic)::value;
+                PB[sl(R + i)] = u;
+                idxA[i] = m;
+                const int y = sA - R + i;
+                if (y == 0) static_for<0, R + i>([&](auto jc) { PB[sl(decltype(jc)::value)] = u; });
+                if (y == H - 1) hold = u;
+            });
+            static_for<0, CH>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if (sA - R + i >= H) PB[sl(R + i)] = hold;
+            });
         }
-        // stage B: its new rows [sB, sB + CH) are stage A's rows just
-        // evaluated; rows outside the image repeat row 0 or row H - 1
-#pragma unroll
-        for (int i = 0; i < CH; ++i) prB[R + i] = outA[i];
-        {
-            const int j0 = R - sB, jH = H - 1 + R - sB;  // window indices of rows 0 and H - 1
-            if (j0 > 0 && j0 < R + CH) {  // uniform
-                const float v0 = prB[0];
-                float top = v0;
-#pragma unroll
-                for (int j = 0; j < R + CH; ++j)
-                    if (j == j0) top = prB[j];
-#pragma unroll
-                for (int j = 0; j < R + CH; ++j)
-                    if (j < j0) prB[j] = top;
-            }
-            if (jH >= 0 && jH < R + CH - 1) {  // uniform
-                float bot = prB[0];
-#pragma unroll
-                for (int j = 0; j < R + CH; ++j)
-                    if (j == jH) bot = prB[j];
-#pragma unroll
-                for (int j = 0; j < R + CH; ++j)
-                    if (j > jH) prB[j] = bot;
-            }
+        // Stage B's row sums read columns [X0 - R, min(W, X0 + TW) + R); at
+        // an image edge the lanes outside the image take column 0 or W - 1
+        // (the clamp), which stage A computed in another lane.
+        if (X0 == 0 || X0 + TW + R > W) {  // uniform
+            if (x == 0) static_for<0, L>([&](auto jc) { Ex[decltype(jc)::value] = PB[sl(decltype(jc)::value)]; });
+            if (x == W - 1) static_for<0, L>([&](auto jc) { Ex[L + decltype(jc)::value] = PB[sl(decltype(jc)::value)]; });
+            __syncthreads();
+            if (x < 0) static_for<0, L>([&](auto jc) { PB[sl(decltype(jc)::value)] = Ex[decltype(jc)::value]; });
+            if (x >= W) static_for<0, L>([&](auto jc) { PB[sl(decltype(jc)::value)] = Ex[L + decltype(jc)::value]; });
         }
-        v_phase(prB, vrB);
+        // stage B: the second sweep
+        v_phase(ph, PB, VB, 2);
         __syncthreads();
-        qh_phase(gB, iB, sB, baseB, QB);
+        qh_phase(ph, gB, iB, sB, QB, 2);
         __syncthreads();
-        if (ownB) eval_phase(gB, sB, baseB, QB, prB, vrB, outB, idxB);
+        if (ownB)
+            eval_phase(ph, gB, sB, QB, VB, 2, [&](auto ic, float u, int m) {
+                constexpr int i = decltype(ic)::value;
+                outB[i] = u;
+                idxB[i] = m;
+            });
         outB_s = sB;
         pending = true;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            prA[i] = prA[CH + i];
-            vrA[i] = vrA[CH + i];
-            prB[i] = prB[CH + i];
-            vrB[i] = vrB[CH + i];
-        }
-        baseA = baseA == 0 ? M : baseA - 1;
-        baseB = baseB == 0 ? M : baseB - 1;
+    };
+
+    for (int n = 0; n < nsteps; n += NRB) {
+        static_for<0, NRB>([&](auto ph) {
+            if (n + decltype(ph)::value < nsteps) step(ph, n + decltype(ph)::value);
+        });
     }
-    if (pending && ownB) store_B();
+    if (pending && ownB) store_prev();
 }
 
 // Waves per SIMD the register allocation must leave room for (the LDS ring
@@ -587,6 +671,10 @@ hipError_t launch_stream(const FwdLaunch &a, hipStream_t stream) {
         if (e != hipSuccess) return e;
     }
     FwdLaunch b = a;
+    // a work item addresses its rows through 32-bit offsets from its first row
+    const long long row_bytes = (long long)a.W * (DT == DT_F32 ? 4 : 2);
+    auto fits = [&](long long rows) { return (rows + 4 * R + 2 * CH) * row_bytes < (1LL << 31); };
+    if (a.th > 0 && !fits(a.th)) return hipErrorInvalidValue;
     if (a.th <= 0) {
         // rows per workgroup chosen so that the strips' chunks fill the
         // device's resident workgroup slots once (no partial last wave)
@@ -607,6 +695,8 @@ hipError_t launch_stream(const FwdLaunch &a, hipStream_t stream) {
         const int per_strip = (int)std::max<long long>(1, n / strips);
         int rows = (a.H + per_strip - 1) / per_strip;
         rows = std::max(CH, (rows + CH - 1) / CH * CH);
+        while (rows > CH && !fits(rows)) rows = std::max(CH, rows / 2 / CH * CH);
+        if (!fits(rows)) return hipErrorInvalidValue;
         b.th = rows;
         b.tiles_y = (a.H + rows - 1) / rows;
     }

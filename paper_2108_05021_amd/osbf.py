@@ -176,6 +176,11 @@ def backward_workspace_size(planes, H, W, r, T, ck: int = 0) -> int:
 
 def osbf_backward(grad_out, grad_in, r: int, T: int, *, sel=None, ckpt=None, ck: int = 0, ws=None):
     """Direct call of the C entry point on preallocated FP32 tensors."""
+    # the C entry point takes FP32 gradients and checkpoints and uint8 maps
+    for name, t, dt in (("grad_out", grad_out, torch.float32), ("grad_in", grad_in, torch.float32),
+                        ("ckpt", ckpt, torch.float32), ("sel", sel, torch.uint8)):
+        if t is not None and t.dtype != dt:
+            raise TypeError(f"osbf_backward: {name} must be {dt}, got {t.dtype}")
     planes, H, W = _geometry(grad_out)
     status = lib().osbf_backward(
         _ptr(grad_out), _ptr(grad_in), planes, H, W, r, T, 0, _ptr(sel), _ptr(ckpt), ck,
@@ -201,6 +206,10 @@ class OSBFFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, r: int, T: int, ckpt_every: int = 0):
+        if x.dtype != torch.float32:
+            # the backward entry point reads FP32 checkpoints; 16-bit storage
+            # has no gradient path
+            raise TypeError(f"OSBFFunction: input must be torch.float32, got {x.dtype}")
         x = x.contiguous()
         if ckpt_every > 0:
             y, ck = forward(x, r, T, ckpt_every=ckpt_every)
@@ -230,6 +239,23 @@ def osbf(x: torch.Tensor, r: int, T: int, ckpt_every: int = 0) -> torch.Tensor:
 
 
 def _images(xs, outs, radii, iters):
+    """The osbf_image list of a batch.  Every image and output must share the
+    first image's dtype and device (the C ABI carries one dtype for the whole
+    batch), each output must match its input's shape, and there must be one
+    radius and one iteration count per image."""
+    xs, outs, radii, iters = list(xs), list(outs), list(radii), list(iters)
+    if not (len(xs) == len(outs) == len(radii) == len(iters)):
+        raise ValueError(f"batch lists differ in length: {len(xs)} images, {len(outs)} outputs, "
+                         f"{len(radii)} radii, {len(iters)} iteration counts")
+    if xs:
+        dt, dev = xs[0].dtype, xs[0].device
+        for i, (x, y) in enumerate(zip(xs, outs)):
+            if x.dtype != dt or y.dtype != dt:
+                raise ValueError(f"image {i}: dtype {x.dtype} / output {y.dtype}, batch dtype is {dt}")
+            if x.device != dev or y.device != dev:
+                raise ValueError(f"image {i}: not on {dev}")
+            if y.shape != x.shape:
+                raise ValueError(f"image {i}: output shape {tuple(y.shape)} != input shape {tuple(x.shape)}")
     arr = (Image * len(xs))()
     for i, (x, y, r, T) in enumerate(zip(xs, outs, radii, iters)):
         planes, H, W = _geometry(x)

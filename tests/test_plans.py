@@ -34,7 +34,7 @@ def test_large_images_use_streaming_plans(shape, r):
     for T in (1, 2, 30):
         p = osbf.forward_plan(*shape, torch.float32, r, T)
         assert p["tile"][1] == 0, (shape, r, T, p)  # streaming: rows chosen at launch
-        assert p["fused"] == (min(2, T) if r <= 2 else 1), (shape, r, T, p)
+        assert p["fused"] == 1, (shape, r, T, p)
         assert p["launches"] == -(-T // p["fused"])
 
 
