@@ -114,6 +114,25 @@ osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t hei
                          void *ckpt, int32_t ck, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * osbf_forward_noalloc -- osbf_forward (no maps, no checkpoints) for callers
+ * that cannot allocate device memory: code under graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It runs the same kernels
+ * and gives the same bits as osbf_forward.  The ping-pong iterate lives in a
+ * library-owned scratch array of OSBF_NOALLOC_SCRATCH_BYTES per device (held
+ * from the first call on a device until the process ends); the call itself
+ * allocates nothing.  Images whose plane set exceeds that size
+ * (planes*H*W*element bytes) return OSBF_ERROR_WORKSPACE before any launch.
+ * Every call on one device shares that device's scratch: calls that overlap
+ * in time on one device (different streams or threads) race and must be
+ * serialised by the caller.
+ */
+#define OSBF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+osbf_status osbf_forward_noalloc(const void *src, void *dst, int32_t planes, int32_t height,
+                                 int32_t width, osbf_dtype dtype, int32_t radius,
+                                 int32_t iterations, osbf_boundary boundary, void *stream);
+
+
+/*
  * osbf_forward_fast -- T sweeps of the fast approximation of Alg. 3
  * (Sec. III-F): only the north-west quadrant mean field is computed per
  * sweep; the four quadrant candidates are its shifts by {0, r}, and each half

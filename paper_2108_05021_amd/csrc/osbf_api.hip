@@ -453,6 +453,54 @@ osbf_status osbf_forward(const void *src, void *dst, int32_t planes, int32_t H, 
                         stream, 0);
 }
 
+}  // extern "C"
+
+// Ping-pong iterate of osbf_forward_noalloc: one array per device, addressed
+// through its device pointer (the name itself is a host-side stand-in).
+static __device__ __align__(256) unsigned char scratch[OSBF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];  // per device, from hipGetSymbolAddress
+
+// The current device's scratch address, looked up once per device.
+osbf_status scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(OSBF_ERROR_UNSUPPORTED, "device %d: scratch kept for devices 0..63", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(OSBF_ERROR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return OSBF_SUCCESS;
+}
+}  // namespace
+
+extern "C" {
+
+osbf_status osbf_forward_noalloc(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
+                                 osbf_dtype dtype, int32_t r, int32_t T, osbf_boundary boundary,
+                                 void *stream) {
+    g_last_error.clear();
+    osbf_status st = check_sizes(planes, H, W, dtype, r, T);
+    if (st != OSBF_SUCCESS) return st;
+    const size_t bytes = (size_t)planes * H * W * elem_bytes(dtype);
+    if (bytes > OSBF_NOALLOC_SCRATCH_BYTES)
+        return fail(OSBF_ERROR_WORKSPACE,
+                    "osbf_forward_noalloc: the image (%zu bytes) exceeds the %zu-byte scratch; "
+                    "use osbf_forward with a workspace", bytes, (size_t)OSBF_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if ((st = scratch_address(&ws)) != OSBF_SUCCESS) return st;
+    return forward_impl(src, dst, planes, H, W, dtype, r, T, boundary, nullptr, nullptr, 0, ws,
+                        OSBF_NOALLOC_SCRATCH_BYTES, stream, 0);
+}
+
 osbf_status osbf_forward_fast(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
                               osbf_dtype dtype, int32_t r, int32_t T, osbf_boundary boundary,
                               void *ws, size_t ws_bytes, void *stream) {

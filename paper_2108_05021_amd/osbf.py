@@ -65,6 +65,8 @@ def lib():
     L.osbf_forward.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int,
                                vp, vp, i32, vp, sz, vp]
     L.osbf_forward.restype = ctypes.c_int
+    L.osbf_forward_noalloc.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int, vp]
+    L.osbf_forward_noalloc.restype = ctypes.c_int
     L.osbf_forward_fast.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int, vp, sz, vp]
     L.osbf_forward_fast.restype = ctypes.c_int
     L.osbf_box_forward.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, ctypes.c_int, vp, sz, vp]
@@ -168,6 +170,20 @@ def forward(x: torch.Tensor, r: int, T: int, *, return_sel: bool = False,
     if ckpt is not None:
         res.append(ckpt)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def forward_noalloc(x: torch.Tensor, r: int, T: int, *, out: torch.Tensor | None = None):
+    """T sweeps through osbf_forward_noalloc: no workspace argument, the
+    library's per-device scratch holds the ping-pong iterate (images up to
+    OSBF_NOALLOC_SCRATCH_BYTES)."""
+    planes, H, W = _geometry(x)
+    y = torch.empty_like(x) if out is None else out
+    _check(lib().osbf_forward_noalloc(_ptr(x), _ptr(y), planes, H, W, DTYPES[x.dtype], r, T, 0,
+                                      _stream(x.device)))
+    return y
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def backward_workspace_size(planes, H, W, r, T, ck: int = 0) -> int:
