@@ -164,3 +164,83 @@ def check_fast_sweep(u_in, u_out, r: int, tol: float = 1e-5):
     dev = np.where(near, np.abs(u_out[..., None] - cand), np.inf).min(axis=2)
     assert dev.max() <= tol, f"fast: value matches no near-minimal candidate (off by {dev.max():.3e})"
     return int((np.abs(u_out - out_o) > tol).sum())
+
+
+def cut_distance(shape, cuts):
+    """Distance of every pixel of a region to its nearest interior cut.
+    ``cuts`` = (top, bottom, left, right): True where that side of the region
+    was cut out of a larger plane (False where it is an image edge, which the
+    clamp reproduces exactly)."""
+    h, w = shape
+    yy, xx = np.mgrid[0:h, 0:w]
+    d = np.full(shape, np.iinfo(np.int64).max // 4, np.int64)
+    top, bottom, left, right = cuts
+    if top:
+        d = np.minimum(d, yy)
+    if bottom:
+        d = np.minimum(d, h - 1 - yy)
+    if left:
+        d = np.minimum(d, xx)
+    if right:
+        d = np.minimum(d, w - 1 - xx)
+    return d
+
+
+def region_of(H, W, y0, x0, size, margin):
+    """Region [ya, yb) x [xa, xb) of a size x size crop grown by ``margin``
+    and clipped to the image, with its cut flags."""
+    ya, yb = max(0, y0 - margin), min(H, y0 + size + margin)
+    xa, xb = max(0, x0 - margin), min(W, x0 + size + margin)
+    return (ya, yb, xa, xb), (ya > 0, yb < H, xa > 0, xb < W)
+
+
+def sweep_region(u_in, u_out, sel, r, cuts, tol=1e-5):
+    """Teacher-forced check of one sweep on a region: pixels at distance >= r
+    from every cut see exactly their windows.  Returns (flips, pixels,
+    max |value - mean of the selected window|); raises on a violation."""
+    u_in = np.asarray(u_in, np.float64)
+    _, sel_o, err, means = oracle.sweep(u_in, r, return_means=True)
+    ok = cut_distance(u_in.shape, cuts) >= r
+    s = np.asarray(sel).astype(np.int64)
+    emin = err.min(axis=2)
+    e_gpu = np.take_along_axis(err, s[..., None], 2)[..., 0]
+    t = tau(r, u_in)
+    gap = np.where(ok, e_gpu - emin, 0.0)
+    assert (gap <= t).all(), f"selection not near-minimal (gap {gap.max():.3e} > tau {t:.3e})"
+    want = np.take_along_axis(means, s[..., None], 2)[..., 0]
+    dev = np.where(ok, np.abs(np.asarray(u_out, np.float64) - want), 0.0)
+    assert dev.max() <= tol, f"value off the selected mean by {dev.max():.3e}"
+    m_o = np.take_along_axis(means, sel_o[..., None].astype(np.int64), 2)[..., 0]
+    flips = int((ok & (s != sel_o) & (np.abs(want - m_o) > tol)).sum())
+    return flips, int(ok.sum()), float(dev.max())
+
+
+def replay_region(u0, u_gpu, sels, r, cuts, tol=1e-5):
+    """The oracle replays the GPU's T selection maps on a region cut out of a
+    larger plane.  At sweep t a pixel's selection is checked (near-minimal
+    for the replayed iterate) where its dependency cone, r * (t + 1) wide,
+    stays inside the region; the final GPU values are compared with the
+    replay where the cone r * T does.  Returns (outliers, max deviation of the
+    final values, value-changing flips against the oracle's own choice,
+    pixels compared at the end)."""
+    u = np.asarray(u0, np.float64)
+    sels = np.asarray(sels)
+    T = sels.shape[0]
+    d = cut_distance(u.shape, cuts)
+    bad = np.zeros(u.shape, bool)
+    flips = 0
+    for t in range(T):
+        s = sels[t].astype(np.int64)
+        _, sel_o, err, means = oracle.sweep(u, r, return_means=True)
+        ok = d >= r * (t + 1)
+        emin = err.min(axis=2)
+        e_gpu = np.take_along_axis(err, s[..., None], 2)[..., 0]
+        bad |= ok & (e_gpu - emin > tau(r, u))
+        nxt = np.take_along_axis(means, s[..., None], 2)[..., 0]
+        m_o = np.take_along_axis(means, sel_o[..., None].astype(np.int64), 2)[..., 0]
+        flips += int((ok & (s != sel_o) & (np.abs(nxt - m_o) > tol)).sum())
+        u = nxt
+    fin = d >= r * T
+    dev = np.where(fin, np.abs(np.asarray(u_gpu, np.float64) - u), 0.0)
+    bad |= dev > tol
+    return int(bad.sum()), float(dev.max()), flips, int(fin.sum())

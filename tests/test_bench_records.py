@@ -46,3 +46,17 @@ def test_records_apply_only_to_their_kernels_and_plans(monkeypatch):
 
 def test_valu_peak_is_the_unpacked_fp32_issue_rate():
     assert abs(bench.VALU_PEAK_TLANE_OPS - 39.3216) < 1e-9
+
+
+def test_parity_record_applies_only_to_its_kernels_and_plans(monkeypatch, tmp_path):
+    rec = {"kernel_hash": "abc", "plans": {"2": [188, 0, 1]}, "headline": {}, "precision": {}}
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "parity_record.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    plans = {2: {"tile": (188, 0), "fused": 1}}
+    assert bench.parity_record(plans) == rec
+    assert bench.parity_record({2: {"tile": (120, 0), "fused": 2}}) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "def")
+    assert bench.parity_record(plans) is None
