@@ -1,0 +1,82 @@
+"""No kernel reads workspace or output memory it has not written: every
+workspace and output buffer is filled with NaN before the call, and the
+results must equal those of a call on fresh buffers bit for bit (a single
+stray read of a NaN would propagate through the window sums)."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2108_05021_amd import osbf, synth
+
+
+def _nan_like(t):
+    out = torch.empty_like(t)
+    if out.dtype.is_floating_point:
+        out.fill_(float("nan"))
+    else:
+        out.fill_(0xAB)
+    return out
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("r,T", [(2, 5), (5, 4), (10, 3), (13, 2)])
+def test_forward_ignores_poisoned_workspace_and_output(dev, dtype, r, T):
+    rng = np.random.default_rng(500 + r)
+    x = torch.from_numpy(synth.voronoi(301, 517, 11, 0.05, rng, C=2)).to(dev).to(dtype)
+    want, wsel, wck = osbf.forward(x, r, T, return_sel=True, ckpt_every=2)
+    planes, H, W = x.shape
+    n = osbf.forward_workspace_size(planes, H, W, dtype, r, T)
+    ws = torch.full((max(n, 4) // 4,), float("nan"), device=dev)
+    y = _nan_like(x)
+    sel = torch.full_like(wsel, 0xAB)
+    ck = _nan_like(wck)
+    osbf.osbf_forward(x, y, r, T, sel=sel, ckpt=ck, ck=2, ws=ws)
+    assert torch.equal(y, want) and torch.equal(sel, wsel) and torch.equal(ck, wck)
+    # in place: the output buffer is the input
+    z = x.clone()
+    ws.fill_(float("nan"))
+    osbf.osbf_forward(z, z, r, T, ws=ws)
+    assert torch.equal(z, want)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("r,T,ck", [(3, 4, 2), (10, 3, 3), (16, 2, 1)])
+def test_backward_ignores_poisoned_workspace(dev, r, T, ck):
+    rng = np.random.default_rng(600 + r)
+    x = torch.from_numpy(synth.voronoi(260, 333, 9, 0.05, rng, C=2)).to(dev)
+    g = torch.from_numpy(rng.normal(size=x.shape).astype(np.float32)).to(dev)
+    _, sel, cks = osbf.forward(x, r, T, return_sel=True, ckpt_every=ck)
+    want = osbf.backward(g, r, T, sel=sel)
+    planes, H, W = x.shape
+    for kw, ckv in (({"sel": sel}, 0), ({"ckpt": cks, "ck": ck}, ck)):
+        n = osbf.backward_workspace_size(planes, H, W, r, T, ckv)
+        ws = torch.full((max(n, 4) // 4,), float("nan"), device=dev)
+        gi = _nan_like(g)
+        osbf.osbf_backward(g, gi, r, T, ws=ws, **kw)
+        assert torch.equal(gi, want), kw.keys()
+
+
+@pytest.mark.gpu
+def test_batched_ignores_poisoned_workspace_and_outputs(dev):
+    rng = np.random.default_rng(700)
+    xs, rs, ts = [], [], []
+    for i in range(12):
+        h, w = int(rng.integers(40, 300)), int(rng.integers(40, 300))
+        xs.append(torch.from_numpy(synth.voronoi(h, w, 7, 0.05, rng, C=1 + i % 3)).to(dev))
+        rs.append([1, 2, 3, 4, 5, 8, 10, 16][i % 8])
+        ts.append(int(rng.integers(1, 7)))
+    want = [osbf.forward(x, r, T) for x, r, T in zip(xs, rs, ts)]
+    outs = [_nan_like(x) for x in xs]
+    L = osbf.lib()
+    imgs = osbf._images(xs, outs, rs, ts)
+    n = L.osbf_batched_workspace_size(imgs, len(xs), 0)
+    ws = torch.full((n,), 0xFF, dtype=torch.uint8, device=dev)   # NaN in every FP32 lane
+    batch = osbf.Batch()
+    osbf._check(L.osbf_batched_prepare(imgs, len(xs), 0, 0, osbf._ptr(ws), n, ctypes.byref(batch),
+                                       osbf._stream(dev)))
+    osbf._check(L.osbf_batched_launch(ctypes.byref(batch), osbf._stream(dev)))
+    for a, b in zip(outs, want):
+        assert torch.equal(a, b)
