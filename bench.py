@@ -431,12 +431,21 @@ def form_variants(reps):
     t = {}
     for name, fn in (("exact", osbf.forward), ("fast", osbf.forward_fast), ("box", osbf.box_forward)):
         t[name] = _timed(lambda: [fn(x, r, T_SWEEPS) for r in RADII], reps)
+    per_r = {}
+    for r in RADII:
+        te = _timed(lambda: osbf.forward(x, r, T_SWEEPS), reps)
+        tb = _timed(lambda: osbf.box_forward(x, r, T_SWEEPS), reps)
+        per_r[str(r)] = {"exact_mpix_it_s": round(x.numel() * T_SWEEPS / te / 1e6, 1),
+                         "box_mpix_it_s": round(x.numel() * T_SWEEPS / tb / 1e6, 1),
+                         "exact_time_over_box": round(te / tb, 3)}
     return {"workload": "3x2048x2048 f32, r in {2,5,10}, T=30 (the bench workload)",
             "exact_mpix_it_s": round(pxit / t["exact"] / 1e6, 1),
             "fast_mpix_it_s": round(pxit / t["fast"] / 1e6, 1),
             "box_mpix_it_s": round(pxit / t["box"] / 1e6, 1),
             "fast_time_over_exact": round(t["fast"] / t["exact"], 3),
             "exact_time_over_box": round(t["exact"] / t["box"], 3),
+            "per_radius": per_r,
+            "box_kernel": "separable two-pass box (vertical running sum in registers, horizontal in LDS)",
             "paper_context": "fast/exact ~0.6 and exact/box ~8 (MATLAB) or ~6 (C++) on a laptop CPU, r unstated"}
 
 

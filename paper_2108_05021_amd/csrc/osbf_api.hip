@@ -510,9 +510,49 @@ osbf_status osbf_forward_fast(const void *src, void *dst, int32_t planes, int32_
 
 osbf_status osbf_box_forward(const void *src, void *dst, int32_t planes, int32_t H, int32_t W,
                              osbf_dtype dtype, int32_t r, int32_t T, osbf_boundary boundary,
-                             void *ws, size_t ws_bytes, void *stream) {
-    return forward_impl(src, dst, planes, H, W, dtype, r, T, boundary, nullptr, nullptr, 0, ws,
-                        ws_bytes, stream, 2);
+                             void *ws, size_t ws_bytes, void *stream_) {
+    // the dedicated separable kernel for its radii; others (and planes too
+    // wide for its 32-bit row offsets) take the box mode of the forward kernels
+    if (!box_radius(r) || T == 0 || !stream_width_ok(W, (int)elem_bytes(dtype), r, stream_step(r)))
+        return forward_impl(src, dst, planes, H, W, dtype, r, T, boundary, nullptr, nullptr, 0, ws,
+                            ws_bytes, stream_, 2);
+    g_last_error.clear();
+    osbf_status st = check_sizes(planes, H, W, dtype, r, T);
+    if (st != OSBF_SUCCESS) return st;
+    if (boundary != OSBF_BOUNDARY_REPLICATE)
+        return fail(OSBF_ERROR_INVALID_VALUE, "unknown boundary %d", (int)boundary);
+    if (!src || !dst) return fail(OSBF_ERROR_INVALID_VALUE, "src and dst must be non-NULL");
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t bytes = (size_t)planes * H * W * elem_bytes(dtype);
+    const bool need_ws = T >= 2 || src == dst;
+    if (need_ws && (!ws || ws_bytes < bytes))
+        return fail(OSBF_ERROR_WORKSPACE, "workspace of %zu bytes required, got %zu", bytes, ws ? ws_bytes : 0);
+    hipError_t e;
+    const void *cur = src;
+    if (src == dst && (T % 2) == 1) {
+        if ((e = hipMemcpyAsync(ws, src, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "copy to workspace");
+        cur = ws;
+    }
+    int tw = 0, step = 0;
+    box_geometry(r, &tw, &step);
+    const int tiles_x = (W + tw - 1) / tw;
+    const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)tiles_x * H)));
+    for (int t = 0; t < T; ++t) {
+        void *out = ((T - 1 - t) % 2 == 0) ? dst : ws;
+        for (int p0 = 0; p0 < planes; p0 += max_planes) {
+            const size_t off = (size_t)p0 * H * W * elem_bytes(dtype);
+            BoxLaunch a;
+            a.src = (const char *)cur + off;
+            a.dst = (char *)out + off;
+            a.planes = std::min(max_planes, planes - p0);
+            a.H = H; a.W = W; a.r = r;
+            a.tw = tw; a.th = 0; a.tiles_x = tiles_x; a.tiles_y = 0;
+            if ((e = launch_box((int)dtype, a, stream)) != hipSuccess) return hip_fail(e, "box filter launch");
+        }
+        cur = out;
+    }
+    return OSBF_SUCCESS;
 }
 
 size_t osbf_backward_workspace_size(int32_t planes, int32_t H, int32_t W, int32_t r, int32_t T,

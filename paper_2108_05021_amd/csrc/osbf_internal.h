@@ -97,6 +97,18 @@ void fwd3d_geometry(int r, int threads, int *tw, int *th);
 size_t fwd3d_lds_bytes(int r, int threads);
 hipError_t launch_forward3d(const Fwd3dLaunch &a, hipStream_t s);
 
+// One sweep of the classical box filter over every plane (the timing
+// baseline): strips of tw columns, th rows per workgroup chosen at launch.
+struct BoxLaunch {
+    const void *src;      // [planes][H][W] storage type
+    void *dst;            // [planes][H][W], never aliases src
+    int planes, H, W, r;
+    int tw, th, tiles_x, tiles_y;
+};
+bool box_radius(int r);                       // radii of the dedicated kernel
+void box_geometry(int r, int *tw, int *step); // strip width, rows per step
+hipError_t launch_box(int dtype, const BoxLaunch &a, hipStream_t s);
+
 // One sweep of the one-sided Gaussian filter over every plane.
 #define OSBF_GAUSS_MAX_R 8
 struct GaussLaunch {
