@@ -276,7 +276,36 @@ osbf_status osbf_autotune(const void *src, void *dst, int32_t planes, int32_t he
                           osbf_dtype dtype, int32_t radius, int32_t iterations, void *stream,
                           int32_t *tile_w, int32_t *tile_h, int32_t *fused);
 
-/* Forget every autotuned plan (later calls use the measured table again). */
+/*
+ * osbf_batched_autotune -- measure the rows per work item of batched launches
+ * (osbf_batched_prepare) for the radii of this batch and keep the fastest per
+ * (device model, dtype, radius).  Candidates 32, 64 and 128 rows, one radius
+ * at a time with the others at their current choice, each timed as the best
+ * of three replays of the whole batch after a warm-up; a candidate must beat
+ * the incumbent (the cached value, else 64 rows) by 3%.  Overwrites the
+ * outputs of the batch (scratch).  ws: device workspace of at least
+ * osbf_batched_autotune_workspace_size() bytes.  rows_out (nullable,
+ * OSBF_MAX_RADIUS + 1 entries) receives the rows chosen per radius (0 for
+ * radii not in the batch).  Blocks until done.  Batches prepared later use
+ * the tuned rows; results do not change (work items give the same bits
+ * whatever their shape).
+ */
+size_t osbf_batched_autotune_workspace_size(const osbf_image *imgs, int32_t n, osbf_dtype dtype);
+osbf_status osbf_batched_autotune(const osbf_image *imgs, int32_t n, osbf_dtype dtype, void *ws,
+                                  size_t ws_bytes, void *stream, int32_t *rows_out);
+
+/*
+ * Forget every autotuned plan and batch shape (later calls use the measured
+ * tables again).  If OSBF_TUNE_CACHE names a file, the file is kept and read
+ * again on the next use of the cache.
+ *
+ * OSBF_TUNE_CACHE (environment): a file the autotune cache is read from on
+ * its first use in a process and written back (whole, atomically replaced)
+ * after every osbf_autotune / osbf_batched_autotune call.  Entries are keyed
+ * by the device's architecture name and CU count, so the file carries over
+ * between processes and machines of one GPU model.  Malformed lines are
+ * ignored.
+ */
 void osbf_autotune_clear(void);
 
 /*

@@ -6,9 +6,10 @@
 // resident slot on the device walks a work list of (image, item) pairs, an
 // item being one row chunk of one strip of one plane (the row-streaming
 // kernel's work unit, 128-lane strips), so small and large images share the
-// machine without per-image launches.  Items of a round are ordered by
-// decreasing radius, and each XCD takes a contiguous slice of the list so
-// neighbouring items of an image meet in the same L2.
+// machine without per-image launches.  The host splits each launch's items
+// over the 8 XCDs by estimated cost (groups of consecutive items of one image,
+// so neighbouring strips meet in one L2, assigned largest first to the least
+// loaded XCD); the workgroups of an XCD take its items round-robin.
 //
 // Every item runs the same code as the single-image streaming kernel; its
 // window sums are position-deterministic, so the batch gives the same bits as
@@ -50,18 +51,15 @@ __device__ __forceinline__ void batched_item(const FwdLaunch &a, int t, float *l
 }
 
 // descs: this round's per-image launch descriptors; items: (image, item)
-// pairs of this round; skip (nullable): items of the round before this
-// launch's share; count: number of items of this launch.
+// pairs of this round; bins: the offsets of this launch's 8 XCD bins in
+// items, and their end (a cost-balanced static partition made on the host).
 template <int DT, int MAXR>
 __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(stream_min_waves(MAXR))))
-void batched_round_kernel(const FwdLaunch *descs, const uint2 *items, const int *skip, const int *count) {
+void batched_round_kernel(const FwdLaunch *descs, const uint2 *items, const int *bins) {
     extern __shared__ float lds[];
-    const int n = *count;
-    if (skip) items += *skip;
     const int nx = gridDim.x >> 3;           // workgroups per XCD (grid is a multiple of 8)
     const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3;
-    const int chunk = (n + 7) >> 3;
-    const int start = xcd * chunk, end = min(n, start + chunk);
+    const int start = bins[xcd], end = bins[xcd + 1];
     for (int it = start + l; it < end; it += nx) {
         const uint2 w = items[it];
         batched_item<DT, MAXR>(descs[w.x], (int)w.y, lds);
@@ -116,14 +114,14 @@ hipError_t batched_slots(int dtype, int maxr, int *slots) {
 }
 
 hipError_t launch_batched_round(int dtype, int maxr, const FwdLaunch *descs, const uint2 *items,
-                                const int *skip, const int *count, int grid, hipStream_t stream) {
+                                const int *bins, int grid, hipStream_t stream) {
     const void *fn = batched_function(dtype, maxr);
     const size_t lds = batched_lds_bytes(maxr);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    void *args[] = {(void *)&descs, (void *)&items, (void *)&skip, (void *)&count};
+    void *args[] = {(void *)&descs, (void *)&items, (void *)&bins};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBatchLanes), args, lds, stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();

@@ -69,13 +69,13 @@ bool adjoint_fixed_tile(int r, int *tw, int *th, size_t *lds_bytes);
 
 // Batched rounds (row-streaming work items, batched_lanes()-wide strips); maxr
 // is the largest radius the launch runs (selects the kernel class, 2, 8 or
-// 16, and its LDS); skip (device, nullable) holds how many of the round's
-// items precede this launch's, count (device) how many it runs.
+// 16, and its LDS); bins (device) holds the offsets of the launch's 8 XCD
+// bins in the round's item list and their end.
 int batched_lanes();
 size_t batched_lds_bytes(int maxr);
 hipError_t batched_slots(int dtype, int maxr, int *slots);
 hipError_t launch_batched_round(int dtype, int maxr, const FwdLaunch *descs, const uint2 *items,
-                                const int *skip, const int *count, int grid, hipStream_t stream);
+                                const int *bins, int grid, hipStream_t stream);
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t s);
 
 // One sweep of the volume filter over every volume: a workgroup per

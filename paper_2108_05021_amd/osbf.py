@@ -96,6 +96,11 @@ def lib():
     L.osbf_gaussian_forward.restype = ctypes.c_int
     L.osbf_autotune.argtypes = [vp, vp, i32, i32, i32, ctypes.c_int, i32, i32, vp] + [ctypes.POINTER(i32)] * 3
     L.osbf_autotune.restype = ctypes.c_int
+    L.osbf_batched_autotune_workspace_size.argtypes = [ctypes.POINTER(Image), i32, ctypes.c_int]
+    L.osbf_batched_autotune_workspace_size.restype = sz
+    L.osbf_batched_autotune.argtypes = [ctypes.POINTER(Image), i32, ctypes.c_int, vp, sz, vp,
+                                        ctypes.POINTER(i32)]
+    L.osbf_batched_autotune.restype = ctypes.c_int
     L.osbf_autotune_clear.argtypes = []
     L.osbf_autotune_clear.restype = None
     _lib = L
@@ -388,6 +393,22 @@ def autotune(x: torch.Tensor, r: int, T: int) -> dict:
     _check(lib().osbf_autotune(_ptr(x), _ptr(scratch), planes, H, W, DTYPES[x.dtype], r, T,
                                _stream(x.device), ctypes.byref(tw), ctypes.byref(th), ctypes.byref(k)))
     return {"tile": (tw.value, th.value), "fused": k.value}
+
+
+def batched_autotune(xs, radii, iters) -> dict:
+    """Tune the rows per batched work item for the radii of this batch
+    (osbf_batched_autotune); returns {radius: rows}.  The batch's outputs are
+    scratch during tuning."""
+    outs = [torch.empty_like(x) for x in xs]
+    dt = DTYPES[xs[0].dtype]
+    imgs = _images(xs, outs, radii, iters)
+    n = lib().osbf_batched_autotune_workspace_size(imgs, len(xs), dt)
+    if n == ctypes.c_size_t(-1).value:
+        _check(lib().osbf_batched_autotune(imgs, len(xs), dt, None, 0, _stream(xs[0].device), None))
+    ws = torch.empty(max(n, 1), dtype=torch.uint8, device=xs[0].device)
+    rows = (ctypes.c_int32 * (MAX_RADIUS + 1))()
+    _check(lib().osbf_batched_autotune(imgs, len(xs), dt, _ptr(ws), n, _stream(xs[0].device), rows))
+    return {r: rows[r] for r in range(MAX_RADIUS + 1) if rows[r]}
 
 
 def autotune_clear() -> None:

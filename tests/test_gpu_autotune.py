@@ -67,3 +67,64 @@ def test_batched_after_autotune_equals_single(dev):
     for x, y, r, t in zip(xs, ys, rs, ts):
         assert torch.equal(y, osbf.forward(x, r, t))
     osbf.autotune_clear()
+
+
+@pytest.mark.gpu
+def test_tune_cache_file_round_trip(dev, tmp_path, monkeypatch):
+    """OSBF_TUNE_CACHE: osbf_autotune writes the cache file; after clearing
+    the in-memory cache the plan is read back from the file; malformed lines
+    are ignored."""
+    path = tmp_path / "osbf_tune.txt"
+    monkeypatch.setenv("OSBF_TUNE_CACHE", str(path))
+    osbf.autotune_clear()
+    try:
+        x = torch.from_numpy(synth.voronoi(1024, 1100, 13, 0.05, np.random.default_rng(77))).to(dev)
+        tuned = osbf.autotune(x, 3, 6)
+        text = path.read_text()
+        assert any(line.startswith("fwd ") for line in text.splitlines()), text
+        p1 = osbf.forward_plan(1, 1024, 1100, torch.float32, 3, 6)
+        assert p1["tile"] == tuned["tile"] and p1["fused"] == tuned["fused"]
+        path.write_text("garbage line\nfwd broken 1 2\n" + text)
+        osbf.autotune_clear()
+        assert osbf.forward_plan(1, 1024, 1100, torch.float32, 3, 6) == p1
+        y = osbf.forward(x, 3, 6)
+        monkeypatch.delenv("OSBF_TUNE_CACHE")
+        osbf.autotune_clear()
+        assert torch.equal(osbf.forward(x, 3, 6), y)
+    finally:
+        monkeypatch.delenv("OSBF_TUNE_CACHE", raising=False)
+        osbf.autotune_clear()
+
+
+@pytest.mark.gpu
+def test_batched_autotune_rows(dev, tmp_path, monkeypatch):
+    """osbf_batched_autotune picks rows per work item for each radius of the
+    batch, persists them, and batches prepared afterwards give the same bits
+    as per-image forwards."""
+    path = tmp_path / "osbf_tune.txt"
+    monkeypatch.setenv("OSBF_TUNE_CACHE", str(path))
+    osbf.autotune_clear()
+    try:
+        rng = np.random.default_rng(78)
+        xs, rs, ts = [], [], []
+        for i in range(10):
+            h, w = int(rng.integers(64, 400)), int(rng.integers(64, 400))
+            xs.append(torch.from_numpy(synth.voronoi(h, w, 7, 0.05, rng, C=1 + i % 2)).to(dev))
+            rs.append([1, 4][i % 2])
+            ts.append(int(rng.integers(2, 6)))
+        rows = osbf.batched_autotune(xs, rs, ts)
+        assert set(rows) == {1, 4} and set(rows.values()) <= {32, 64, 128}
+        lines = [line for line in path.read_text().splitlines() if line.startswith("batch ")]
+        assert len(lines) == 2
+        want = [osbf.forward(x, r, T) for x, r, T in zip(xs, rs, ts)]
+        for a, b in zip(osbf.batched(xs, rs, ts), want):
+            assert torch.equal(a, b)
+        # a hand-written shape from the file: the bits do not change
+        model = lines[0].split()[1]
+        path.write_text(f"batch {model} 0 1 32\nbatch {model} 0 4 128\n")
+        osbf.autotune_clear()
+        for a, b in zip(osbf.batched(xs, rs, ts), want):
+            assert torch.equal(a, b)
+    finally:
+        monkeypatch.delenv("OSBF_TUNE_CACHE", raising=False)
+        osbf.autotune_clear()
