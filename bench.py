@@ -388,11 +388,28 @@ def form_small(reps):
             if not torch.equal(out, want):
                 raise RuntimeError("graph replay differs from the eager forward")
         t_graph = _timed(g.replay, n, warmup=20)
+        # ten calls in one graph: a graph launch's fixed cost is then paid
+        # once per ten calls
+        g10 = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(g10, stream=st):
+                for _ in range(10):
+                    call()
+        torch.cuda.current_stream().wait_stream(st)
+        out.zero_()
+        g10.replay()
+        torch.cuda.synchronize()
+        if not torch.equal(out, want):
+            raise RuntimeError("graph replay differs from the eager forward")
+        t_graph10 = _timed(g10.replay, max(1, n // 10), warmup=3) / 10
         plan = osbf.forward_plan(planes, H, W, torch.float32, r, T)
         res[tag] = {"plan": {"tile": list(plan["tile"]), "fused": plan["fused"], "launches": plan["launches"]},
                     "eager_us": round(t_eager * 1e6, 2), "graph_us": round(t_graph * 1e6, 2),
+                    "graph_10_calls_us_per_call": round(t_graph10 * 1e6, 2),
+                    "graph_launch_overhead_us": round((t_graph - t_graph10) * 1e6 * 10 / 9, 2),
                     "eager_mpix_it_s": round(x.numel() * T / t_eager / 1e6, 1),
-                    "graph_mpix_it_s": round(x.numel() * T / t_graph / 1e6, 1)}
+                    "graph_mpix_it_s": round(x.numel() * T / t_graph / 1e6, 1),
+                    "graph_10_calls_mpix_it_s": round(x.numel() * T / t_graph10 / 1e6, 1)}
 
     measure("table")
     osbf.autotune(x, r, T)

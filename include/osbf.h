@@ -159,7 +159,9 @@ osbf_status osbf_box_forward(const void *src, void *dst, int32_t planes, int32_t
 /*
  * Workspace bytes osbf_backward needs: one FP32 plane set for the gradient
  * ping-pong, plus (checkpoint mode, ck > 0) two FP32 plane sets and
- * min(ck, T) uint8 maps for recomputing one segment.  (size_t)-1 if invalid.
+ * min(ck, T) uint8 maps for recomputing one segment, plus for radii above 16
+ * three FP32 planes of (H + 2r) x (W + 4r) per plane for the two-pass
+ * adjoint.  (size_t)-1 if invalid.
  */
 size_t osbf_backward_workspace_size(int32_t planes, int32_t height, int32_t width,
                                     int32_t radius, int32_t iterations, int32_t ck);
@@ -170,6 +172,8 @@ size_t osbf_backward_workspace_size(int32_t planes, int32_t height, int32_t widt
  * this is its exact derivative).  Each sweep's transpose scatters the
  * upstream gradient of a pixel, divided by the size of its selected window,
  * over that window's clamped pixels; it is computed as a gather (no atomics).
+ * Every radius osbf_forward accepts (0..OSBF_MAX_RADIUS): r <= 16 in LDS-
+ * resident kernels, larger radii in two passes through the workspace.
  *
  *   grad_out   device FP32 [planes][H][W], gradient w.r.t. the output U^T.
  *   grad_in    device FP32 [planes][H][W], gradient w.r.t. the input U^0;

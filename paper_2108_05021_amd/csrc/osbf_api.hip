@@ -659,6 +659,8 @@ size_t osbf_backward_workspace_size(int32_t planes, int32_t H, int32_t W, int32_
     const size_t P = (size_t)planes * H * W;
     size_t n = P * sizeof(float);                        // gradient ping-pong
     if (ck > 0) n += 2 * P * sizeof(float) + (size_t)std::min(ck, T) * P;  // recompute buffers, maps
+    if (r > kAdjointLdsMaxR)  // the two-pass adjoint's planes, after the rest (256-byte aligned)
+        n = (n + 255) / 256 * 256 + adjoint_global_ws_bytes(planes, H, W, r);
     return n;
 }
 
@@ -689,13 +691,22 @@ osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes,
     if (!ws || ws_bytes < need)
         return fail(OSBF_ERROR_WORKSPACE, "workspace of %zu bytes required, got %zu", need, ws ? ws_bytes : 0);
 
-    BwdLaunch b;
-    if (!adjoint_tile(r, &b))
+    BwdLaunch b{};
+    const bool global_pass = r > kAdjointLdsMaxR;  // beyond the LDS-resident kernels
+    float *wglob = nullptr;
+    if (global_pass) {
+        const size_t base = osbf_backward_workspace_size(planes, H, W, r, T, ckpt ? ck : 0) -
+                            adjoint_global_ws_bytes(planes, H, W, r);
+        wglob = (float *)((char *)ws + base);
+        b.tw = W; b.th = H;
+    } else if (!adjoint_tile(r, &b)) {
         return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
+    }
     b.H = H; b.W = W; b.r = r;
     b.tiles_x = (W + b.tw - 1) / b.tw;
     b.tiles_y = (H + b.th - 1) / b.th;
-    const int max_planes = std::max(1, (int)(((1LL << 31) - 1) / ((long long)b.tiles_x * b.tiles_y)));
+    const int max_planes = global_pass ? 65535
+                                       : std::max(1, (int)(((1LL << 31) - 1) / ((long long)b.tiles_x * b.tiles_y)));
 
     float *wsg = (float *)ws;
     float *f1 = nullptr, *f2 = nullptr;
@@ -720,7 +731,7 @@ osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes,
             b.gnext = gin + off;
             b.sel = sel_t + off;
             b.g = gout + off;
-            hipError_t err = launch_adjoint(b, stream);
+            hipError_t err = global_pass ? launch_adjoint_global(b, wglob, stream) : launch_adjoint(b, stream);
             if (err != hipSuccess) return err;
         }
         gin = gout;

@@ -22,6 +22,8 @@
 // Running sums restart at image positions that are multiples of r (direct
 // sum, then slides), as in the forward kernels, so results do not depend on
 // the tile shape.
+#include <algorithm>
+
 #include "osbf_device.h"
 #include "osbf_internal.h"
 
@@ -193,6 +195,135 @@ __global__ __launch_bounds__(256) void adjoint_kernel(BwdLaunch a) {
             g[(size_t)y * W + x] = acc;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass adjoint through global memory for radii beyond the LDS-resident
+// kernels (r > 16; their tile grown by 2r on every side no longer fits LDS).
+// Pass 1, one thread per (F column, block of r q rows): the masked vertical
+// sums of adjoint_kernel's phase A for q rows [-r, H + r) and F columns
+// [-2r, W + 2r), into three workspace planes (VL+VF, VR+VF, VF).  Pass 2, one
+// thread per output pixel: Gpad at every q of its clamp preimage (the
+// horizontal sums of phase B, anchored at the same multiples of r), folded
+// in phase C's order.  Same FP32 operations and order as adjoint_kernel.
+__global__ __launch_bounds__(256) void adjoint_global_vert(const float *gnext, const uint8_t *sel, float *hl,
+                                                           float *hr, float *vf, int H, int W, int r) {
+    const int FW = W + 4 * r, QH = H + 2 * r;
+    const int x = (int)(blockIdx.x * 256 + threadIdx.x) - 2 * r;  // F column
+    const int plane = blockIdx.z;
+    if (x >= W + 2 * r) return;
+    const int nblk = (QH + r - 1) / r;
+    for (int b = blockIdx.y; b < nblk; b += gridDim.y) {  // blocks of r q rows
+    const int y0 = -r + b * r, y1 = min(y0 + r, H + r);
+    const size_t poff = (size_t)plane * H * W;
+    const float *gn = gnext + poff;
+    const uint8_t *sl = sel + poff;
+    const float inv_h = 1.0f / (float)((r + 1) * (2 * r + 1));
+    const float inv_q = 1.0f / (float)((r + 1) * (r + 1));
+    const bool xin = x >= 0 && x < W;
+    auto at = [&](int y, int &s, float &g) {
+        if (xin && y >= 0 && y < H) {
+            const size_t gi = (size_t)y * W + x;
+            s = sl[gi];
+            g = gn[gi] * (s >= 4 ? inv_q : inv_h);
+        } else {
+            s = 0;
+            g = 0.f;
+        }
+    };
+    int s;
+    float g;
+    at(y0 - r, s, g);
+    float u1 = pick(M_C1, s, g), u3 = pick(M_C3, s, g), ud = pick(M_FD, s, g);
+    for (int yy = y0 - r + 1; yy <= y0; ++yy) {
+        at(yy, s, g);
+        u1 += pick(M_C1, s, g); u3 += pick(M_C3, s, g); ud += pick(M_FD, s, g);
+    }
+    at(y0, s, g);
+    float d2 = pick(M_C2, s, g), d4 = pick(M_C4, s, g), du = pick(M_FU, s, g);
+    for (int yy = y0 + 1; yy <= y0 + r; ++yy) {
+        at(yy, s, g);
+        d2 += pick(M_C2, s, g); d4 += pick(M_C4, s, g); du += pick(M_FU, s, g);
+    }
+    const size_t qoff = (size_t)plane * QH * FW;
+    for (int y = y0; y < y1; ++y) {
+        if (y > y0) {
+            int sn, so;
+            float gn_, go;
+            at(y, sn, gn_);
+            at(y - r - 1, so, go);
+            u1 += pick(M_C1, sn, gn_) - pick(M_C1, so, go);
+            u3 += pick(M_C3, sn, gn_) - pick(M_C3, so, go);
+            ud += pick(M_FD, sn, gn_) - pick(M_FD, so, go);
+            at(y + r, sn, gn_);
+            at(y - 1, so, go);
+            d2 += pick(M_C2, sn, gn_) - pick(M_C2, so, go);
+            d4 += pick(M_C4, sn, gn_) - pick(M_C4, so, go);
+            du += pick(M_FU, sn, gn_) - pick(M_FU, so, go);
+        }
+        at(y, s, g);
+        const float v = ud + du;
+        const float vl = u1 + d2 - pick(M_FR, s, g);
+        const float vr = u3 + d4 - pick(M_FL, s, g);
+        const size_t o = qoff + (size_t)(y + r) * FW + (x + 2 * r);
+        hl[o] = vl + v;
+        hr[o] = vr + v;
+        vf[o] = v;
+    }
+    }
+}
+
+__global__ __launch_bounds__(256) void adjoint_global_horiz(const float *hl, const float *hr, const float *vf,
+                                                            float *gout, int H, int W, int r) {
+    const int FW = W + 4 * r, QH = H + 2 * r;
+    const int x = (int)(blockIdx.x * 256 + threadIdx.x), plane = blockIdx.z;
+    if (x >= W) return;
+    for (int y = blockIdx.y; y < H; y += gridDim.y) {
+    const size_t qoff = (size_t)plane * QH * FW;
+    // Gpad at q = (qx, qy): horizontal sums anchored at the multiple of r at
+    // or left of qx (a direct sum there, then slides), as phase B
+    auto gpad = [&](int qx, int qy) {
+        const float *L = hl + qoff + (size_t)(qy + r) * FW + 2 * r;  // + q column
+        const float *Rr = hr + qoff + (size_t)(qy + r) * FW + 2 * r;
+        const float *V = vf + qoff + (size_t)(qy + r) * FW + 2 * r;
+        const int x0 = qx - (((qx % r) + r) % r);
+        float sl_ = L[x0 - r], sr_ = Rr[x0];
+        for (int xx = x0 - r + 1; xx <= x0; ++xx) sl_ += L[xx];
+        for (int xx = x0 + 1; xx <= x0 + r; ++xx) sr_ += Rr[xx];
+        for (int xx = x0 + 1; xx <= qx; ++xx) {
+            sl_ += L[xx] - L[xx - r - 1];
+            sr_ += Rr[xx + r] - Rr[xx - 1];
+        }
+        return sl_ + sr_ - V[qx];
+    };
+    const int ya = y == 0 ? -r : y, yb = y == H - 1 ? H - 1 + r : y;
+    const int xa = x == 0 ? -r : x, xb = x == W - 1 ? W - 1 + r : x;
+    float acc;
+    if (ya == yb && xa == xb) {
+        acc = gpad(x, y);
+    } else {
+        acc = 0.f;
+        for (int qy = ya; qy <= yb; ++qy)
+            for (int qx = xa; qx <= xb; ++qx) acc += gpad(qx, qy);
+    }
+    gout[(size_t)plane * H * W + (size_t)y * W + x] = acc;
+    }
+}
+
+size_t adjoint_global_ws_bytes(int planes, int H, int W, int r) {
+    return (size_t)3 * planes * (size_t)(H + 2 * r) * (size_t)(W + 4 * r) * sizeof(float);
+}
+
+hipError_t launch_adjoint_global(const BwdLaunch &a, float *ws, hipStream_t stream) {
+    const size_t plane_q = (size_t)(a.H + 2 * a.r) * (a.W + 4 * a.r);
+    float *hl = ws, *hr = ws + plane_q * a.planes, *vf = ws + 2 * plane_q * a.planes;
+    const dim3 g1((a.W + 4 * a.r + 255) / 256, std::min((a.H + 2 * a.r + a.r - 1) / a.r, 65535), a.planes);
+    hipLaunchKernelGGL(adjoint_global_vert, g1, dim3(256), 0, stream, a.gnext, a.sel, hl, hr, vf, a.H, a.W, a.r);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2((a.W + 255) / 256, std::min(a.H, 65535), a.planes);
+    hipLaunchKernelGGL(adjoint_global_horiz, g2, dim3(256), 0, stream, hl, hr, vf, a.g, a.H, a.W, a.r);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -77,6 +77,11 @@ hipError_t batched_slots(int dtype, int maxr, int *slots);
 hipError_t launch_batched_round(int dtype, int maxr, const FwdLaunch *descs, const uint2 *items,
                                 const int *bins, int grid, hipStream_t stream);
 hipError_t launch_adjoint(const BwdLaunch &a, hipStream_t s);
+// Radii above kAdjointLdsMaxR: the two-pass adjoint through global memory,
+// whose workspace (three planes of the grown q region per plane) is `ws`.
+constexpr int kAdjointLdsMaxR = 16;
+size_t adjoint_global_ws_bytes(int planes, int H, int W, int r);
+hipError_t launch_adjoint_global(const BwdLaunch &a, float *ws, hipStream_t s);
 
 // One sweep of the volume filter over every volume: a workgroup per
 // (volume, slice chunk, tile); tiles are tw x (threads / 64) voxel columns.

@@ -43,7 +43,7 @@ def test_forward_ignores_poisoned_workspace_and_output(dev, dtype, r, T):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("r,T,ck", [(3, 4, 2), (10, 3, 3), (16, 2, 1)])
+@pytest.mark.parametrize("r,T,ck", [(3, 4, 2), (10, 3, 3), (16, 2, 1), (24, 2, 1)])
 def test_backward_ignores_poisoned_workspace(dev, r, T, ck):
     rng = np.random.default_rng(600 + r)
     x = torch.from_numpy(synth.voronoi(260, 333, 9, 0.05, rng, C=2)).to(dev)
