@@ -408,14 +408,15 @@ hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, u
 // fixed-geometry tiled kernel, then the smallest square region of the generic
 // kernel that fits the device's LDS.  OSBF_ADJOINT=fixed or generic forces
 // the tiled kernels (tests compare all of them bit for bit).
-bool adjoint_tile(int r, BwdLaunch *b) {
+bool adjoint_tile(int r, int W, BwdLaunch *b) {
     const char *env = getenv("OSBF_ADJOINT");
     const bool force_generic = env && strcmp(env, "generic") == 0;
     const bool force_fixed = env && strcmp(env, "fixed") == 0;
     b->fixed = 0;
     size_t fixed_lds = 0;
+    // (the streaming kernel addresses a chunk's rows through 32-bit offsets)
     if (!force_generic && !force_fixed && adjoint_stream_tile(r, &b->tw, &b->th, &fixed_lds) &&
-        fixed_lds <= lds_limit()) {
+        fixed_lds <= lds_limit() && (long long)(b->th + 6 * r) * W * 4 < (1LL << 31)) {
         b->fixed = 2;
         b->pitch = b->arr = 0;
         return true;
@@ -699,7 +700,7 @@ osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes,
                             adjoint_global_ws_bytes(planes, H, W, r);
         wglob = (float *)((char *)ws + base);
         b.tw = W; b.th = H;
-    } else if (!adjoint_tile(r, &b)) {
+    } else if (!adjoint_tile(r, W, &b)) {
         return fail(OSBF_ERROR_UNSUPPORTED, "radius %d does not fit the device's LDS", r);
     }
     b.H = H; b.W = W; b.r = r;

@@ -549,17 +549,24 @@ static hipError_t launch_adjoint_fixed(const BwdLaunch &a, hipStream_t stream) {
 // columns and a chunk of output rows of one plane (lane = region column
 // X0 - 2R + lane) and walks down the chunk's q rows CH = M*R at a time.  Per
 // step (q rows [s, s + CH)): the lane's gv and selection rows [s - R, s + CH
-// + R) live in registers (2R carried over, CH loaded one step ahead); the
-// vertical pass forms VL+VF, VR+VF and VF there, block by block, and writes
-// them to LDS; the horizontal pass (each lane's (row, column block) items,
-// the same every step) forms Gpad over VF; then each lane folds and stores
-// the output rows these q rows complete.
-// VF/Gpad is double-buffered by step parity, so a step costs two barriers.
-// The block anchors, the FP32 operations and the fold order are those of the
+// + R) live in a register ring; the vertical pass forms VL+VF, VR+VF and VF
+// there, block by block, and writes them to LDS; the horizontal pass (each
+// lane's (row, column block) items, the same every step) forms Gpad over VF;
+// then each lane folds and stores the output rows these q rows complete.
+// The ring's origin advances by CH rows per step, so the step is unrolled
+// over the ring period and every ring slot is a compile-time constant; the
+// next step's rows are loaded (buffer loads, scalar row offsets) straight
+// into the slots of rows the vertical pass no longer needs, and converted to
+// gv in place when the step that uses them begins.  VF/Gpad is
+// double-buffered by step parity, so a step costs two barriers.  The
+// block anchors, the FP32 operations and the fold order are those of the
 // tiled adjoint kernels, so the results are bit-identical to theirs.
 template <int R, int RW, int M>
 __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
     constexpr int PITCH = RW + 1, CH = M * R;
+    constexpr int L = CH + 2 * R;                 // ring rows
+    static_assert(M == 1, "one block of R rows per step");
+    constexpr int NPH = L / CH;                   // ring period in steps (3)
     extern __shared__ float lds[];
     float *const HL = lds;                   // CH rows
     float *const HR = lds + CH * PITCH;      // CH rows
@@ -573,10 +580,6 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
     const int X0 = strip * TW, Y0 = chunk * YC;
     const int ox = X0 - 2 * R;  // image column of LDS column 0
     const int x = ox + lx;
-    const size_t plane_off = (size_t)plane * H * W;
-    const float *gn = a.gnext + plane_off;
-    const uint8_t *sl = a.sel + plane_off;
-    float *gout = a.g + plane_off;
 
     // q region (the chunk grown by R beyond every image edge it touches) and
     // the F columns it reads
@@ -590,6 +593,23 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
     const int fxa = x == 0 ? -R : x, fxb = x == W - 1 ? W - 1 + R : x;  // fold columns
     const float inv_h = 1.0f / (float)((R + 1) * (2 * R + 1));
     const float inv_q = 1.0f / (float)((R + 1) * (R + 1));
+    const int nsteps = (qy1 - qy0 + CH - 1) / CH;
+
+    // rows this item reads (clamped) and writes, as buffer resources with
+    // 32-bit offsets from row0
+    const int row0 = max(0, qy0 - R);
+    const int row1 = min(H, qy0 + nsteps * CH + R);
+    const size_t first = (size_t)plane * H * W + (size_t)row0 * W;
+    const uint32_t nrow = (uint32_t)(row1 - row0) * (uint32_t)W;
+    const BufRsrc rg = buf_rsrc(a.gnext + first, nrow * 4);
+    const BufRsrc rs = buf_rsrc(a.sel + first, nrow);
+    const BufRsrc ro_ = buf_rsrc(a.g + first, nrow * 4);
+    auto ld_g = [&](int y) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, xc * 4, (clampi(y, 0, H - 1) - row0) * W * 4, 0));
+    };
+    auto ld_s = [&](int y) {
+        return (int)__builtin_amdgcn_raw_buffer_load_b8(rs, xc, (clampi(y, 0, H - 1) - row0) * W, 0);
+    };
 
     // this lane's horizontal items: (row, block of R columns), rows of one
     // block of R rows consecutive, row fastest; CH * nb <= M * (TW + 2R) <=
@@ -607,71 +627,60 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
         it_x0[k] = qx0 + b * R;
     }
 
-    float g[CH + 2 * R];  // gv of rows [s - R, s + CH + R) of this lane's column
-    int s_[CH + 2 * R];   // their selections (0 outside the image)
-    float graw[CH];
-    uint8_t sraw[CH];
-    auto load_rows = [&](int y0) {  // rows [y0, y0 + CH), clamped into the image
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const size_t gi = (size_t)min(max(y0 + j, 0), H - 1) * W + xc;
-            graw[j] = gn[gi];
-            sraw[j] = sl[gi];
-        }
-    };
-    auto convert = [&](int j, int yy, float gr, int sr) {
+    // ring of gv and selection of rows [s - R, s + CH + R) of this lane's
+    // column (selection 0 and gv 0 outside the image); raw loaded values
+    // until converted
+    float G[L];
+    int S_[L];
+    auto convert = [&](int slot, int yy) {
         const bool in = xin && yy >= 0 && yy < H;
-        s_[j] = in ? sr : 0;
-        g[j] = in ? gr * (s_[j] >= 4 ? inv_q : inv_h) : 0.f;
+        const int sr = S_[slot];
+        S_[slot] = in ? sr : 0;
+        G[slot] = in ? G[slot] * (S_[slot] >= 4 ? inv_q : inv_h) : 0.f;
     };
-    // rows [qy0 - R, qy0 + R), then the first lookahead rows
-    load_rows(qy0 - R);
 #pragma unroll
-    for (int j = 0; j < 2 * R; ++j) {
-        if (j < CH) {
-            convert(j, qy0 - R + j, graw[j], sraw[j]);
-        } else {  // CH < 2R (M = 1): the rest of the 2R rows
-            const size_t gi = (size_t)min(max(qy0 - R + j, 0), H - 1) * W + xc;
-            convert(j, qy0 - R + j, gn[gi], sl[gi]);
-        }
+    for (int j = 0; j < L; ++j) {
+        G[j] = ld_g(qy0 - R + j);
+        S_[j] = ld_s(qy0 - R + j);
     }
-    load_rows(qy0 + R);
-
-    const int nsteps = (qy1 - qy0 + CH - 1) / CH;
-    float acc = 0.f;  // fold of the output row being accumulated
-    for (int n = 0; n < nsteps; ++n) {
-        const int s0 = qy0 + n * CH;
-        float *const VF = VF0 + (n & 1) * CH * PITCH;
 #pragma unroll
-        for (int j = 0; j < CH; ++j) convert(2 * R + j, s0 + R + j, graw[j], sraw[j]);
-        if (n + 1 < nsteps) load_rows(s0 + CH + R);
+    for (int j = 0; j < 2 * R; ++j) convert(j, qy0 - R + j);
+
+    float acc = 0.f;  // fold of the output row being accumulated
+    auto step = [&](auto ph, int n) {
+        constexpr int PH = decltype(ph)::value;
+        auto sl = [](int j) { return (j + PH * CH) % L; };  // logical j <-> row s0 - R + j
+        const int s0 = qy0 + n * CH;
+        float *const VF = VF0 + (n & 1) * CH * PITCH;  // by step parity
+#pragma unroll
+        for (int j = 0; j < CH; ++j) convert(sl(2 * R + j), s0 + R + j);
         // vertical pass: the operations of adjoint_fixed_kernel's block, for
         // the M blocks of R rows of this step
 #pragma unroll
         for (int mb = 0; mb < M; ++mb) {
             const int y0 = s0 + mb * R;
             if (!vcol || y0 >= qy1) continue;  // the row condition is uniform
-            const int *s = s_ + mb * R;        // rows [y0 - R, y0 + 2R)
-            const float *gb = g + mb * R;
-            float u1 = pick(M_C1, s[0], gb[0]), u3 = pick(M_C3, s[0], gb[0]), ud = pick(M_FD, s[0], gb[0]);
+            auto sv = [&](int j) { return S_[sl(mb * R + j)]; };  // rows [y0 - R, y0 + 2R)
+            auto gv = [&](int j) { return G[sl(mb * R + j)]; };
+            float u1 = pick(M_C1, sv(0), gv(0)), u3 = pick(M_C3, sv(0), gv(0)), ud = pick(M_FD, sv(0), gv(0));
 #pragma unroll
             for (int j = 1; j <= R; ++j) {
-                u1 += pick(M_C1, s[j], gb[j]);
-                u3 += pick(M_C3, s[j], gb[j]);
-                ud += pick(M_FD, s[j], gb[j]);
+                u1 += pick(M_C1, sv(j), gv(j));
+                u3 += pick(M_C3, sv(j), gv(j));
+                ud += pick(M_FD, sv(j), gv(j));
             }
-            float d2 = pick(M_C2, s[R], gb[R]), d4 = pick(M_C4, s[R], gb[R]), du = pick(M_FU, s[R], gb[R]);
+            float d2 = pick(M_C2, sv(R), gv(R)), d4 = pick(M_C4, sv(R), gv(R)), du = pick(M_FU, sv(R), gv(R));
 #pragma unroll
             for (int j = R + 1; j <= 2 * R; ++j) {
-                d2 += pick(M_C2, s[j], gb[j]);
-                d4 += pick(M_C4, s[j], gb[j]);
-                du += pick(M_FU, s[j], gb[j]);
+                d2 += pick(M_C2, sv(j), gv(j));
+                d4 += pick(M_C4, sv(j), gv(j));
+                du += pick(M_FU, sv(j), gv(j));
             }
             auto emit = [&](int tt) {
                 const int j = R + tt;
                 const float vf = ud + du;
-                const float vl = u1 + d2 - pick(M_FR, s[j], gb[j]);
-                const float vr = u3 + d4 - pick(M_FL, s[j], gb[j]);
+                const float vl = u1 + d2 - pick(M_FR, sv(j), gv(j));
+                const float vr = u3 + d4 - pick(M_FL, sv(j), gv(j));
                 const int o = (mb * R + tt) * PITCH + lx;
                 HL[o] = vl + vf;
                 HR[o] = vr + vf;
@@ -682,14 +691,23 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
             for (int tt = 1; tt < R; ++tt) {
                 if (y0 + tt < qy1) {  // uniform
                     const int nn = R + tt, od = tt - 1, n2 = 2 * R + tt, od2 = R + tt - 1;
-                    u1 += pick(M_C1, s[nn], gb[nn]) - pick(M_C1, s[od], gb[od]);
-                    u3 += pick(M_C3, s[nn], gb[nn]) - pick(M_C3, s[od], gb[od]);
-                    ud += pick(M_FD, s[nn], gb[nn]) - pick(M_FD, s[od], gb[od]);
-                    d2 += pick(M_C2, s[n2], gb[n2]) - pick(M_C2, s[od2], gb[od2]);
-                    d4 += pick(M_C4, s[n2], gb[n2]) - pick(M_C4, s[od2], gb[od2]);
-                    du += pick(M_FU, s[n2], gb[n2]) - pick(M_FU, s[od2], gb[od2]);
+                    u1 += pick(M_C1, sv(nn), gv(nn)) - pick(M_C1, sv(od), gv(od));
+                    u3 += pick(M_C3, sv(nn), gv(nn)) - pick(M_C3, sv(od), gv(od));
+                    ud += pick(M_FD, sv(nn), gv(nn)) - pick(M_FD, sv(od), gv(od));
+                    d2 += pick(M_C2, sv(n2), gv(n2)) - pick(M_C2, sv(od2), gv(od2));
+                    d4 += pick(M_C4, sv(n2), gv(n2)) - pick(M_C4, sv(od2), gv(od2));
+                    du += pick(M_FU, sv(n2), gv(n2)) - pick(M_FU, sv(od2), gv(od2));
                     emit(tt);
                 }
+            }
+        }
+        // the next step's rows [s0 + CH + R, s0 + 2CH + R) into the slots of
+        // rows [s0 - R, s0 - R + CH), which the vertical pass no longer needs
+        if (n + 1 < nsteps) {
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                G[sl(j)] = ld_g(s0 + CH + R + j);
+                S_[sl(j)] = ld_s(s0 + CH + R + j);
             }
         }
         __syncthreads();
@@ -700,24 +718,26 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
             if (!it_ok[k] || s0 + it_t[k] >= qy1) continue;
             const int ro = it_t[k] * PITCH - ox;  // + image column
             const int x0 = it_x0[k];
+            const float *hlp = HL + ro + x0 - R, *hrp = HR + ro + x0;
             float hl[2 * R], hr[2 * R];
 #pragma unroll
             for (int i = 0; i < 2 * R; ++i) {
-                hl[i] = HL[ro + x0 - R + i];
-                hr[i] = HR[ro + min(x0 + i, qx1 + R - 1)];
+                hl[i] = hlp[i];
+                hr[i] = hrp[i];  // past the F columns only where the slide below is skipped
             }
             float sl_ = hl[0], sr_ = hr[0];
 #pragma unroll
             for (int i = 1; i <= R; ++i) sl_ += hl[i];
 #pragma unroll
             for (int i = 1; i <= R; ++i) sr_ += hr[i];
-            VF[ro + x0] = sl_ + sr_ - VF[ro + x0];
+            float *vp = VF + ro + x0;
+            vp[0] = sl_ + sr_ - vp[0];
 #pragma unroll
             for (int tt = 1; tt < R; ++tt) {
                 if (x0 + tt < qx1) {
                     sl_ += hl[R + tt] - hl[tt - 1];
                     sr_ += hr[R + tt] - hr[tt - 1];
-                    VF[ro + x0 + tt] = sl_ + sr_ - VF[ro + x0 + tt];
+                    vp[tt] = sl_ + sr_ - vp[tt];
                 }
             }
         }
@@ -734,20 +754,21 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
                 const int yo = min(max(qy, 0), H - 1);
                 const int ya = yo == 0 ? -R : yo, yb = yo == H - 1 ? H - 1 + R : yo;
                 const float *gp = VF + tt * PITCH - ox;  // + image column
+                const int so = (yo - row0) * W * 4;
                 if (ya == yb && fxa == fxb) {
-                    gout[(size_t)yo * W + x] = gp[x];
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(gp[x]), ro_, x * 4, so, 0);
                 } else {
                     if (qy == ya) acc = 0.f;
                     for (int qx = fxa; qx <= fxb; ++qx) acc += gp[qx];
-                    if (qy == yb) gout[(size_t)yo * W + x] = acc;
+                    if (qy == yb) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc), ro_, x * 4, so, 0);
                 }
             }
         }
-#pragma unroll
-        for (int j = 0; j < 2 * R; ++j) {
-            g[j] = g[CH + j];
-            s_[j] = s_[CH + j];
-        }
+    };
+    for (int n = 0; n < nsteps; n += NPH) {
+        static_for<0, NPH>([&](auto ph) {
+            if (n + decltype(ph)::value < nsteps) step(ph, n + decltype(ph)::value);
+        });
     }
 }
 
@@ -770,6 +791,7 @@ constexpr int kAdjStreamRows = 24;
 // / 270 K, r=5 257 K / 202 K / 228 K, r=16 65 K / 62 K / 75 K).
 constexpr int adj_stream_lanes(int r) { return r == 16 ? 256 : r == 3 ? 192 : 128; }
 
+// HL, HR and two VF buffers, CH rows each.
 static size_t adjoint_stream_lds_bytes(int r) {
     return (size_t)4 * adj_step_blocks(r) * r * (adj_stream_lanes(r) + 1) * sizeof(float);
 }
