@@ -134,6 +134,94 @@ def parity_record(plans):
     return d
 
 
+def _counter_rows(path):
+    """Per-kernel mean of every counter per dispatch from a rocprofv3
+    --pmc --output-format csv directory."""
+    import csv
+    sums, disp = {}, {}
+    for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                k = row["Kernel_Name"]
+                sums.setdefault(k, {}).setdefault(row["Counter_Name"], 0.0)
+                sums[k][row["Counter_Name"]] += float(row["Counter_Value"])
+                disp.setdefault(k, set()).add(row["Dispatch_Id"])
+    return {k: {c: v / len(disp[k]) for c, v in cs.items()} for k, cs in sums.items()}, \
+        {k: len(v) for k, v in disp.items()}
+
+
+def write_counter_records(path):
+    """Write profiles/fwd_traffic.json and profiles/fwd_valu.json from the
+    rocprofv3 counter runs of the timed step under `path` (subdirectories
+    fetch, write: FETCH_SIZE / WRITE_SIZE of `bench.py --steps 1 --warmup 1
+    --no-cpu-baseline --no-forms`; copy_fetch, copy_write: the same of
+    `bench.py --copy-calibration`; sq: SQ_INSTS_VALU of the step).  The
+    records carry the forward sources' hash and the plans, so bench.py uses
+    them only while both still hold."""
+    import re
+
+    import torch
+
+    from paper_2108_05021_amd import osbf
+    plans = {r: osbf.forward_plan(C, H, W, torch.float32, r, T_SWEEPS) for r in RADII}
+    pat = re.compile(r"osbf::fwd_(?:stream2?|fixed)_kernel<0, (\d+),")
+
+    def by_radius(sub, counter):
+        rows, _ = _counter_rows(os.path.join(path, sub))
+        out = {}
+        for k, cs in rows.items():
+            m = pat.search(k)
+            if m and counter in cs:
+                out[int(m.group(1))] = cs[counter]
+        return out
+
+    def copy_kib(sub, counter):
+        rows, _ = _counter_rows(os.path.join(path, sub))
+        vals = [cs[counter] for k, cs in rows.items() if "copyBuffer" in k and counter in cs]
+        if not vals:
+            raise SystemExit(f"no device copy dispatch with {counter} under {sub}")
+        return max(vals)
+
+    copy_kib_total = (64 << 20) * 4 / 1024
+    ff = copy_kib_total / copy_kib("copy_fetch", "FETCH_SIZE")
+    wf = copy_kib_total / copy_kib("copy_write", "WRITE_SIZE")
+    fetch, write = by_radius("fetch", "FETCH_SIZE"), by_radius("write", "WRITE_SIZE")
+    per = {f"r{r}_k{plans[r]['fused']}": round((fetch[r] * ff + write[r] * wf) * 1024) for r in RADII}
+    launches = sum(plans[r]["launches"] for r in RADII)
+    per["rgb2048_T30"] = round(sum(per[f"r{r}_k{plans[r]['fused']}"] * plans[r]["launches"] for r in RADII)
+                               / launches)
+    step = "python bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-forms"
+    cmd = "rocprofv3 --pmc {c} --output-format csv -d " + path.rstrip("/") + "/{d} -o pmc -- {p}"
+    common = {"kernel_hash": kernel_source_hash(), "plans": plan_signature(plans)}
+    traffic = {
+        "about": f"HBM-side bytes per launch of the forward kernels on the {C}x{H}x{W} FP32 workload "
+                 f"(r in {set(RADII)}, T={T_SWEEPS}), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per "
+                 f"dispatch) scaled by a plain 256 MiB device copy (factors {ff:.2f} and {wf:.2f}).  Valid "
+                 "only for the forward kernel sources with this hash and these launch plans.",
+        **common, "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+        "fetch_kib": {str(r): round(fetch[r], 1) for r in RADII},
+        "write_kib": {str(r): round(write[r], 1) for r in RADII},
+        "per_launch_bytes": per,
+        "commands": [cmd.format(c="FETCH_SIZE", d="fetch", p=step), cmd.format(c="WRITE_SIZE", d="write", p=step),
+                     cmd.format(c="FETCH_SIZE", d="copy_fetch", p="python bench.py --copy-calibration"),
+                     cmd.format(c="WRITE_SIZE", d="copy_write", p="python bench.py --copy-calibration")]}
+    valu = by_radius("sq", "SQ_INSTS_VALU")
+    pxs = C * H * W
+    valu_rec = {
+        "about": f"VALU lane-operations per pixel-sweep of the forward kernels on the {C}x{H}x{W} FP32 workload: "
+                 "rocprofv3 SQ_INSTS_VALU (wave instructions per dispatch) x 64 lanes / (pixels x sweeps "
+                 "per launch).  Valid only for the forward kernel sources with this hash and these launch plans.",
+        **common,
+        "lane_ops_per_px_sweep": {str(r): round(valu[r] * 64 / (pxs * plans[r]["fused"]), 2) for r in RADII},
+        "command": cmd.format(c="SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+                                "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR", d="sq", p=step)}
+    for name, rec in (("fwd_traffic.json", traffic), ("fwd_valu.json", valu_rec)):
+        with open(os.path.join(ROOT, "profiles", name), "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+    print(json.dumps({"traffic": per, "valu": valu_rec["lane_ops_per_px_sweep"]}))
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -505,7 +593,13 @@ def main():
                     help="run only this form (for profiling it) and print its result; no timed step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (for scaling HBM counters)")
+    ap.add_argument("--counter-records", metavar="DIR", default=None,
+                    help="write profiles/fwd_traffic.json and fwd_valu.json from the rocprofv3 counter "
+                         "runs under DIR (no GPU needed)")
     args = ap.parse_args()
+    if args.counter_records:
+        write_counter_records(args.counter_records)
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(64 << 20, device="cuda")
