@@ -95,12 +95,12 @@ __global__ __launch_bounds__(kBoxLanes) void box_stream_kernel(BoxLaunch a) {
         if (out_s - R >= Y0 && out_s - R + CH <= yb) {  // uniform
             int o = (out_s - R - row0) * rowb;
 #pragma unroll
-            for (int i = 0; i < CH; ++i, o += rowb) S::store(dst, vst, o, out[i]);
+            for (int i = 0; i < CH; ++i, o += rowb) S::store_bits(dst, vst, o, out[i]);
         } else {
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const int y = out_s - R + i;
-                if (y >= Y0 && y < yb) S::store(dst, vst, (y - row0) * rowb, out[i]);
+                if (y >= Y0 && y < yb) S::store_bits(dst, vst, (y - row0) * rowb, out[i]);
             }
         }
     };
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBoxLanes) void box_stream_kernel(BoxLaunch a) {
         __syncthreads();
         if (own) {
 #pragma unroll
-            for (int i = 0; i < CH; ++i) out[i] = S::round(Ss[i * PITCH + lx] * inv);
+            for (int i = 0; i < CH; ++i) out[i] = S::bits(Ss[i * PITCH + lx] * inv);
         }
         out_s = s;
         pending = true;

@@ -25,7 +25,9 @@ __device__ __forceinline__ BufRsrc buf_rsrc(const void *base, uint32_t bytes) {
 
 // Besides cvt/load/pack/round, each storage type has buffer forms: load_raw
 // returns the stored bits in an FP32 register (the value itself for F32),
-// from_raw converts them, store rounds and writes one element.
+// from_raw converts them, store rounds and writes one element.  bits rounds
+// a value to the storage type and keeps the result in the form store_bits
+// writes without converting again (for a value that is only stored).
 template <> struct Storage<DT_F32> {
     using T = float;
     static __device__ __forceinline__ float cvt(T v) { return v; }
@@ -39,6 +41,8 @@ template <> struct Storage<DT_F32> {
     static __device__ __forceinline__ void store(BufRsrc r, int voff, int soff, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
     }
+    static __device__ __forceinline__ float bits(float v) { return v; }
+    static __device__ __forceinline__ void store_bits(BufRsrc r, int voff, int soff, float b) { store(r, voff, soff, b); }
 };
 
 template <> struct Storage<DT_F16> {
@@ -63,6 +67,13 @@ template <> struct Storage<DT_F16> {
     static __device__ __forceinline__ void store(BufRsrc r, int voff, int soff, float v) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, pack(v)), r, voff, soff, 0);
     }
+    // the F16 bits in the low half
+    static __device__ __forceinline__ float bits(float v) {
+        return __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, pack(v)));
+    }
+    static __device__ __forceinline__ void store_bits(BufRsrc r, int voff, int soff, float b) {
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__float_as_uint(b), r, voff, soff, 0);
+    }
 };
 
 template <> struct Storage<DT_BF16> {
@@ -84,6 +95,14 @@ template <> struct Storage<DT_BF16> {
     static __device__ __forceinline__ float from_raw(float v) { return __uint_as_float(__float_as_uint(v) << 16); }
     static __device__ __forceinline__ void store(BufRsrc r, int voff, int soff, float v) {
         __builtin_amdgcn_raw_buffer_store_b16(pack(v), r, voff, soff, 0);
+    }
+    // the rounded BF16 in the high half (the low half is not cleared)
+    static __device__ __forceinline__ float bits(float v) {
+        uint32_t u = __float_as_uint(v);
+        return __uint_as_float(u + 0x7FFFu + ((u >> 16) & 1u));
+    }
+    static __device__ __forceinline__ void store_bits(BufRsrc r, int voff, int soff, float b) {
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(__float_as_uint(b) >> 16), r, voff, soff, 0);
     }
 };
 

@@ -154,14 +154,14 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
     auto store_step = [&]() {
         auto put = [&](int i) {
             const int y = out_s - R + i;
-            S::store(io.dst, vst, io.st_off(y), out_v[i]);
+            S::store_bits(io.dst, vst, io.st_off(y), out_v[i]);
             if (SEL) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)out_i[i], io.sel, x, io.sel_off(y), 0);
         };
         if (out_s - R >= Y0 && out_s - R + CH <= yb) {  // uniform: offsets step by a row
             int o = io.st_off(out_s - R), os = io.sel_off(out_s - R);
 #pragma unroll
             for (int i = 0; i < CH; ++i, o += rowb, os += W) {
-                S::store(io.dst, vst, o, out_v[i]);
+                S::store_bits(io.dst, vst, o, out_v[i]);
                 if (SEL) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)out_i[i], io.sel, x, os, 0);
             }
         } else {
@@ -284,7 +284,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
                 const float nw = Qr[ou + lx], ne = Qr[ou + lx + R], sw = Qr[od + lx], se = Qr[od + lx + R];
                 const float vu = VR[sl(i)], vd = VR[sl(i + R)];
                 if constexpr (MODE == MODE_BOX) {
-                    out_v[i] = S::round(box_sum(nw, ne, sw, se, Sg[oh + lx], Sg[oh + lx + R], vu, vd, c) * inv_box);
+                    out_v[i] = S::bits(box_sum(nw, ne, sw, se, Sg[oh + lx], Sg[oh + lx + R], vu, vd, c) * inv_box);
                     out_i[i] = 0;
                 } else {
                     float d[8];
@@ -293,7 +293,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
                     else
                         exact_distances(d, nw, ne, sw, se, Sg[oh + lx], Sg[oh + lx + R], vu, vd, c, fr1, f2r1, N);
                     const Pick pk = select8<SEL>(d);
-                    out_v[i] = S::round(fmaf(pk.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c));
+                    out_v[i] = S::bits(fmaf(pk.d, MODE == MODE_FAST ? 0.5f / (fr1 * fr1) : invN, c));
                     out_i[i] = pk.idx;
                 }
             };
