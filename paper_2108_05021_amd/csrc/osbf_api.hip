@@ -125,11 +125,12 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 // Measured defaults for the compiled radii (3x2048x2048 FP32, T=30 on
 // MI355X, plan sweep over geometries, fusion depths, streaming strip widths
 // and rows per workgroup, 0 = chosen to fill the device once), in order of
-// preference: the row-streaming kernel, one sweep per launch (the fused
-// two-sweep kernel measured 3-4% slower at r = 1 and 2); the later entries
-// are fallbacks for devices whose LDS does not fit the first.
+// preference: the row-streaming kernel, one sweep per launch, except at
+// r = 1, where the fused two-sweep kernel is 6-10% faster (20.4-21.1 against
+// 21.6-23.4 us per sweep; at r = 2 it is 5% slower, at r = 3 even); the
+// later entries are fallbacks for devices whose LDS does not fit the first.
 struct TunedShape { int r, geom, k, rows; };
-const TunedShape kTuned[] = {{1, GEOM_S128, 1, 0}, {1, GEOM_64x48, 3, 0},
+const TunedShape kTuned[] = {{1, GEOM_S128, 2, 0}, {1, GEOM_64x48, 3, 0},
                              {2, GEOM_S192, 1, 0}, {2, GEOM_64x48, 2, 0},
                              {3, GEOM_S128, 1, 0}, {3, GEOM_64x48, 2, 0},
                              {4, GEOM_S192, 1, 0}, {4, GEOM_64x48, 1, 0},
