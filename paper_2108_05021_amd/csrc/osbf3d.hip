@@ -111,7 +111,9 @@ template <int R, int NT, bool SEL>
 __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
     constexpr int RW = 64, PITCH = RW + 1, NY = NT / RW, TH = NY, RH = TH + 2 * R;
     constexpr int ARR = RH * PITCH, RING = 2 * R + 1;
-    constexpr int MB = ((TH + R + R - 1) / R + NY - 1) / NY;  // column blocks per wave, at most
+    // vertical blocks start at multiples of R at or above the tile's first
+    // row: at most TH + 2R - 1 rows of them
+    constexpr int MB = ((TH + 2 * R - 1 + R - 1) / R + NY - 1) / NY;  // column blocks per wave, at most
     extern __shared__ float lds[];
     float *const Q = lds + 4 * ARR;
     float *const Hs = lds + 5 * ARR;
@@ -137,12 +139,17 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
     uint8_t *sel = SEL ? a.sel + (size_t)vol * D * slice : nullptr;
 
     // this thread's (x, y) column; its vertical blocks of R rows (V on rows
-    // [ya, yb+R), columns [max(0,xa-R), min(W,xb+R))) and their 2R input rows
+    // [yv, yb+R), columns [max(0,xa-R), min(W,xb+R))) and their 2R input
+    // rows.  The blocks start at yv, the last multiple of R at or before ya, and
+    // the row-sum items at xa, a multiple of R (TW is one), so every running
+    // sum restarts at the same image coordinates whatever the tile shape,
+    // and a voxel's bits do not depend on the workgroup size or the chunking.
     const int x = ox + lx, y = Y0 + ly;
     const bool own = x >= xa && x < xb && y < yb;
     const bool vx = x >= max(0, xa - R) && x < min(W, xb + R);
     const int yend = yb + R;
-    const int nblk = (yend - ya + R - 1) / R;
+    const int yv = ya - ya % R;
+    const int nblk = (yend - yv + R - 1) / R;
     float raw[MB][2 * R];
     auto load_rows = [&](int zs) {
         const float *sl_ = src + (size_t)min(max(zs, 0), D - 1) * slice;
@@ -151,7 +158,7 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
             for (int i = 0; i < MB; ++i) {
                 const int b = ly + i * NY;
                 if (b < nblk) {
-                    const int y0 = ya + b * R;
+                    const int y0 = yv + b * R;
 #pragma unroll
                     for (int tt = 0; tt < 2 * R; ++tt)
                         raw[i][tt] = sl_[(size_t)min(max(y0 - R + tt, 0), H - 1) * W + x];
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
         for (int i = 0; i < MB; ++i) {
             const int b = ly + i * NY;
             if (b >= nblk) break;
-            const int y0 = ya + b * R;
+            const int y0 = yv + b * R;
             const float *p = raw[i];
 #pragma unroll
             for (int tt = 0; tt < R; ++tt) {
@@ -293,8 +300,9 @@ int fwd3d_threads(int r) {
     return r >= 4 ? 1024 : 512;
 }
 
+// Tiles are a multiple of r columns wide (the row sums' anchors).
 void fwd3d_geometry(int r, int threads, int *tw, int *th) {
-    *tw = 64 - 2 * r;
+    *tw = (64 - 2 * r) / r * r;
     *th = threads / 64;
 }
 

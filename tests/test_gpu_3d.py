@@ -69,6 +69,26 @@ def test_sweep_parity(dev, monkeypatch, shape, r, threads):
     assert flips <= max(2, int(0.001 * cur.numel())), f"{flips} value-changing near-tie flips"
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_bits_independent_of_tile_and_chunk(dev, monkeypatch, r):
+    """Every running sum restarts at image coordinates that are multiples of r
+    and the z-sums are direct, so values and maps do not depend on the
+    workgroup size (tiles of 8 or 16 rows) or on the slices per chunk."""
+    x = torch.from_numpy(_vol((2, 45, 53, 71), 700 + r)).to(dev)
+    runs = []
+    for threads in ("512", "1024"):
+        for slices in ("", "5", "13"):
+            monkeypatch.setenv("OSBF_3D_THREADS", threads)
+            if slices:
+                monkeypatch.setenv("OSBF_3D_SLICES", slices)
+            else:
+                monkeypatch.delenv("OSBF_3D_SLICES", raising=False)
+            runs.append(((threads, slices), osbf.forward3d(x, r, 3, return_sel=True)))
+    (k0, (y0, s0)) = runs[0]
+    for k, (y, s) in runs[1:]:
+        assert torch.equal(y, y0) and torch.equal(s, s0), (k0, k)
+
+
 def test_multi_sweep_equals_chained_single_sweeps(dev):
     """T sweeps in one call equal T single-sweep calls bit for bit (the
     ping-pong through the workspace changes nothing), also in place."""
