@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define OSBF_ABI_VERSION 1
+#define OSBF_ABI_VERSION 2
 #define OSBF_MAX_RADIUS 32          /* largest supported r */
 #define OSBF3D_MAX_RADIUS 4         /* largest r of the volume filter */
 #define OSBF_GAUSS_MAX_RADIUS 8     /* largest r of the one-sided Gaussian filter */
@@ -192,11 +192,21 @@ osbf_status osbf_backward(const float *grad_out, float *grad_in, int32_t planes,
                           int32_t ck, void *ws, size_t ws_bytes, void *stream);
 
 /* One image of a batch: `planes` independent H x W planes, its own radius
- * and iteration count.  src and dst are device pointers and must differ. */
+ * and iteration count.  src and dst are device pointers and must differ.
+ * Strides are in elements, each 0 for the contiguous layout: element
+ * (p, y, x) of src is at src + p * src_plane_stride + y * src_row_stride + x
+ * (likewise dst), so crops and other views of larger planes are read and
+ * written in place.  A non-zero row stride must be >= width, a non-zero
+ * plane stride >= height * row stride (planes do not overlap); src and dst
+ * must not overlap.  A row stride whose rows overflow the kernels' 32-bit
+ * offsets is OSBF_ERROR_UNSUPPORTED.  The library's own extra iterate per
+ * image (in the workspace) is contiguous. */
 typedef struct {
     const void *src;
     void *dst;
     int32_t planes, height, width, radius, iterations;
+    int64_t src_plane_stride, src_row_stride;
+    int64_t dst_plane_stride, dst_row_stride;
 } osbf_image;
 
 /* A prepared batch (caller-owned plain data; see osbf_batched_prepare). */

@@ -884,6 +884,17 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
         if (st != OSBF_SUCCESS) return fail(st, "image %d: %s", j, g_last_error.c_str());
         if (!m.src || !m.dst) return fail(OSBF_ERROR_INVALID_VALUE, "image %d: NULL pointer", j);
         if (m.src == m.dst) return fail(OSBF_ERROR_INVALID_VALUE, "image %d: src and dst must differ", j);
+        for (int side = 0; side < 2; ++side) {
+            const int64_t ld = side ? m.dst_row_stride : m.src_row_stride;
+            const int64_t ps = side ? m.dst_plane_stride : m.src_plane_stride;
+            const int64_t rows = ld ? ld : m.width;
+            if (ld < 0 || (ld && ld < m.width) || ld > INT32_MAX)
+                return fail(OSBF_ERROR_INVALID_VALUE, "image %d: %s row stride %lld (width %d)", j,
+                            side ? "dst" : "src", (long long)ld, m.width);
+            if (ps < 0 || (ps && m.planes > 1 && ps < (int64_t)m.height * rows))
+                return fail(OSBF_ERROR_INVALID_VALUE, "image %d: %s plane stride %lld < height x row stride", j,
+                            side ? "dst" : "src", (long long)ps);
+        }
         BatchImagePlan &b = L->img[j];
         if (m.radius == 0 || m.iterations == 0) {
             L->identity++;
@@ -894,8 +905,10 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
         const int r = m.radius, step = stream_step(r);
         b.tw = ((batched_lanes() - 2 * r) / r) * r;
         b.th = (std::min(m.height, batch_rows(r, (int)dtype, rows_override)) + step - 1) / step * step;
-        if (!stream_width_ok(m.width, (int)elem_bytes(dtype), r, b.th))
-            return fail(OSBF_ERROR_UNSUPPORTED, "image %d: width %d too large for the batched kernel", j, m.width);
+        const int64_t ld_max = std::max<int64_t>(m.width, std::max(m.src_row_stride, m.dst_row_stride));
+        if (!stream_width_ok((int)ld_max, (int)elem_bytes(dtype), r, b.th))
+            return fail(OSBF_ERROR_UNSUPPORTED, "image %d: row of %lld elements too long for the batched kernel", j,
+                        (long long)ld_max);
         b.rounds = m.iterations;
         L->maxr = std::max(L->maxr, r);
         const int64_t tiles = (int64_t)((m.width + b.tw - 1) / b.tw) * ((m.height + b.th - 1) / b.th);
@@ -961,11 +974,20 @@ static osbf_status batched_prepare_impl(const osbf_image *imgs, int32_t n, osbf_
         const osbf_image &m = imgs[j];
         void *buf = (char *)ws + L.buf_off[j];
         const void *cur = m.src;
+        int cur_ld = (int)m.src_row_stride;   // the workspace iterate is contiguous (0)
+        long long cur_ps = m.src_plane_stride;
         for (int r = 0; r < b.rounds; ++r) {
-            void *out = ((b.rounds - 1 - r) % 2 == 0) ? m.dst : buf;
+            const bool to_dst = (b.rounds - 1 - r) % 2 == 0;
+            void *out = to_dst ? m.dst : buf;
             FwdLaunch &a = descs[(size_t)r * n + j];
             a.src = cur;
             a.dst = out;
+            a.src_ld = cur_ld;
+            a.src_ps = cur_ps;
+            a.dst_ld = to_dst ? (int)m.dst_row_stride : 0;
+            a.dst_ps = to_dst ? m.dst_plane_stride : 0;
+            cur_ld = a.dst_ld;
+            cur_ps = a.dst_ps;
             a.sel = nullptr;
             a.sel_stride = 0;
             a.planes = m.planes;
@@ -1086,9 +1108,21 @@ osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype, os
     if (st != OSBF_SUCCESS) return st;
     hipStream_t stream = (hipStream_t)stream_;
     for (int j = 0; j < n; ++j) {
-        if (imgs[j].radius == 0 || imgs[j].iterations == 0) {
-            const size_t bytes = (size_t)imgs[j].planes * imgs[j].height * imgs[j].width * elem_bytes(dtype);
-            hipError_t e = hipMemcpyAsync(imgs[j].dst, imgs[j].src, bytes, hipMemcpyDeviceToDevice, stream);
+        const osbf_image &m = imgs[j];
+        if (m.radius == 0 || m.iterations == 0) {
+            const size_t es = elem_bytes(dtype), row = (size_t)m.width * es;
+            const size_t sld = m.src_row_stride ? (size_t)m.src_row_stride * es : row;
+            const size_t dld = m.dst_row_stride ? (size_t)m.dst_row_stride * es : row;
+            const size_t sps = m.src_plane_stride ? (size_t)m.src_plane_stride * es : sld * m.height;
+            const size_t dps = m.dst_plane_stride ? (size_t)m.dst_plane_stride * es : dld * m.height;
+            hipError_t e = hipSuccess;
+            if (sld == row && dld == row && sps == row * m.height && dps == row * m.height) {
+                e = hipMemcpyAsync(m.dst, m.src, row * m.height * m.planes, hipMemcpyDeviceToDevice, stream);
+            } else {
+                for (int p = 0; p < m.planes && e == hipSuccess; ++p)
+                    e = hipMemcpy2DAsync((char *)m.dst + p * dps, dld, (const char *)m.src + p * sps, sld, row,
+                                         m.height, hipMemcpyDeviceToDevice, stream);
+            }
             if (e != hipSuccess) return hip_fail(e, "copy");
         }
     }

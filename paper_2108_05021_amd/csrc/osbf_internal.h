@@ -17,6 +17,10 @@ struct FwdLaunch {
     int tiles_x, tiles_y;
     int pitch, arr;       // LDS row pitch and per-array size, in floats
     int geom;             // LDS geometry (Geom)
+    // Strided src / dst (the streaming kernels only; 0 = contiguous): row and
+    // plane strides in elements.  Maps are always contiguous.
+    int src_ld = 0, dst_ld = 0;
+    long long src_ps = 0, dst_ps = 0;
 };
 
 // LDS geometries: fixed regions compiled for the common radii, the generic

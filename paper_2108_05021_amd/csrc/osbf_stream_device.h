@@ -40,15 +40,35 @@ constexpr int stream_step_rows(int r) {
 
 // Rows [row0, row1) of one plane that a work item touches, as buffer
 // resources of the iterate (and of the map): every access is a 32-bit lane
-// offset plus a scalar row offset from row0.
+// offset plus a scalar row offset from row0.  The iterate's rows may be
+// strided (src and dst each their own row and plane strides); maps are
+// contiguous.
 struct ItemRows {
     BufRsrc src, dst, sel;
     int row0, H, W;
-    int es;  // bytes per element of the iterate
-    __device__ __forceinline__ int ld_off(int y) const { return (clampi(y, 0, H - 1) - row0) * W * es; }
-    __device__ __forceinline__ int st_off(int y) const { return (y - row0) * W * es; }
+    int srow, drow;  // bytes per row of the iterate read / written
+    __device__ __forceinline__ int ld_off(int y) const { return (clampi(y, 0, H - 1) - row0) * srow; }
+    __device__ __forceinline__ int st_off(int y) const { return (y - row0) * drow; }
     __device__ __forceinline__ int sel_off(int y) const { return (y - row0) * W; }
 };
+
+template <typename T>
+__device__ __forceinline__ ItemRows item_rows(const FwdLaunch &a, int plane, int row0, int row1, bool sel) {
+    ItemRows io;
+    io.H = a.H;
+    io.W = a.W;
+    io.row0 = row0;
+    const int sld = a.src_ld ? a.src_ld : a.W, dld = a.dst_ld ? a.dst_ld : a.W;
+    const long long sps = a.src_ps ? a.src_ps : (long long)a.H * a.W;
+    const long long dps = a.dst_ps ? a.dst_ps : (long long)a.H * a.W;
+    io.srow = sld * (int)sizeof(T);
+    io.drow = dld * (int)sizeof(T);
+    const uint32_t nr = (uint32_t)(row1 - row0);
+    io.src = buf_rsrc((const T *)a.src + plane * sps + (long long)row0 * sld, nr * (uint32_t)io.srow);
+    io.dst = buf_rsrc((T *)a.dst + plane * dps + (long long)row0 * dld, nr * (uint32_t)io.drow);
+    io.sel = sel ? buf_rsrc(a.sel + (size_t)plane * a.H * a.W + (size_t)row0 * a.W, nr * (uint32_t)a.W) : io.dst;
+    return io;
+}
 
 // MODE: MODE_EXACT, MODE_FAST (quadrant means only, no H field) or MODE_BOX,
 // as in the tiled kernels; maps (SEL) only with MODE_EXACT.
@@ -96,19 +116,8 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
     const bool own = x >= xa && x < xb;
     const int nsteps = (yend - Y0 + CH - 1) / CH;
 
-    ItemRows io;
-    io.H = H;
-    io.W = W;
-    io.es = (int)sizeof(T);
-    io.row0 = max(0, Y0 - R);
-    {
-        const int row1 = min(H, Y0 + nsteps * CH);  // past the last row loaded or stored
-        const size_t first = (size_t)plane * H * W + (size_t)io.row0 * W;
-        const uint32_t n = (uint32_t)(row1 - io.row0) * (uint32_t)W;
-        io.src = buf_rsrc((const T *)a.src + first, n * sizeof(T));
-        io.dst = buf_rsrc((T *)a.dst + first, n * sizeof(T));
-        io.sel = SEL ? buf_rsrc(a.sel + first, n) : io.dst;
-    }
+    // rows up to the last one loaded or stored
+    const ItemRows io = item_rows<T>(a, plane, max(0, Y0 - R), min(H, Y0 + nsteps * CH), SEL);
     const int vld = clampi(x, 0, W - 1) * (int)sizeof(T);  // this lane's column (clamped)
     const int vst = x * (int)sizeof(T);
 
@@ -150,7 +159,6 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
     int out_i[CH];
     int out_s = 0;
     bool pending = false;
-    const int rowb = W * (int)sizeof(T);
     auto store_step = [&]() {
         auto put = [&](int i) {
             const int y = out_s - R + i;
@@ -160,7 +168,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
         if (out_s - R >= Y0 && out_s - R + CH <= yb) {  // uniform: offsets step by a row
             int o = io.st_off(out_s - R), os = io.sel_off(out_s - R);
 #pragma unroll
-            for (int i = 0; i < CH; ++i, o += rowb, os += W) {
+            for (int i = 0; i < CH; ++i, o += io.drow, os += W) {
                 S::store_bits(io.dst, vst, o, out_v[i]);
                 if (SEL) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)out_i[i], io.sel, x, os, 0);
             }
@@ -205,7 +213,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
             if (s + 2 * CH <= H) {  // uniform: no clamped row, offsets step by a row
                 int o = io.ld_off(s + CH);
 #pragma unroll
-                for (int i = 0; i < CH; ++i, o += rowb) PR[sl(i)] = S::load_raw(io.src, vld, o);
+                for (int i = 0; i < CH; ++i, o += io.srow) PR[sl(i)] = S::load_raw(io.src, vld, o);
             } else {
 #pragma unroll
                 for (int i = 0; i < CH; ++i) PR[sl(i)] = S::load_raw(io.src, vld, io.ld_off(s + CH + i));
@@ -371,19 +379,8 @@ __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, floa
     const bool ownA = x >= gA.xa && x < gA.xb, ownB = x >= gB.xa && x < gB.xb;
     const int nsteps = (yb + 2 * R - gA.ya + CH - 1) / CH;
 
-    ItemRows io;
-    io.H = H;
-    io.W = W;
-    io.es = (int)sizeof(T);
-    io.row0 = max(0, gA.ya - R);
-    {
-        const int row1 = min(H, gA.ya + nsteps * CH);  // past the last row loaded or stored
-        const size_t first = (size_t)plane * H * W + (size_t)io.row0 * W;
-        const uint32_t n = (uint32_t)(row1 - io.row0) * (uint32_t)W;
-        io.src = buf_rsrc((const T *)a.src + first, n * sizeof(T));
-        io.dst = buf_rsrc((T *)a.dst + first, n * sizeof(T));
-        io.sel = SEL ? buf_rsrc(a.sel + first, n) : io.dst;
-    }
+    // rows up to the last one loaded or stored
+    const ItemRows io = item_rows<T>(a, plane, max(0, gA.ya - R), min(H, gA.ya + nsteps * CH), SEL);
     BufRsrc selB = io.sel;
     if (SEL) {
         const size_t first = (size_t)plane * H * W + (size_t)io.row0 * W;
@@ -434,12 +431,11 @@ __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, floa
     float hold = 0.f;  // stage A's row H - 1 (bottom chunks)
     int outB_s = 0;
     bool pending = false;
-    const int rowb = W * (int)sizeof(T);
     auto store_prev = [&]() {
         if (!SEL && outB_s - R >= Y0 && outB_s - R + CH <= yb) {  // uniform: offsets step by a row
             int o = io.st_off(outB_s - R);
 #pragma unroll
-            for (int i = 0; i < CH; ++i, o += rowb) S::store(io.dst, vst, o, outB[i]);
+            for (int i = 0; i < CH; ++i, o += io.drow) S::store(io.dst, vst, o, outB[i]);
             return;
         }
 #pragma unroll
@@ -573,7 +569,7 @@ __device__ __forceinline__ void fwd_stream2_item(const FwdLaunch &a, int t, floa
             if (sA + CH >= 0 && sA + 2 * CH <= H) {  // uniform: no clamped row
                 int o = io.ld_off(sA + CH);
 #pragma unroll
-                for (int i = 0; i < CH; ++i, o += rowb) PA[sl(i)] = S::load_raw(io.src, vld, o);
+                for (int i = 0; i < CH; ++i, o += io.srow) PA[sl(i)] = S::load_raw(io.src, vld, o);
             } else {
 #pragma unroll
                 for (int i = 0; i < CH; ++i) PA[sl(i)] = S::load_raw(io.src, vld, io.ld_off(sA + CH + i));

@@ -24,10 +24,12 @@ _lib = None
 
 
 class Image(ctypes.Structure):
-    """osbf_image: one image of a batch."""
+    """osbf_image: one image of a batch (strides in elements, 0 = contiguous)."""
     _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("planes", ctypes.c_int32),
                 ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("radius", ctypes.c_int32),
-                ("iterations", ctypes.c_int32)]
+                ("iterations", ctypes.c_int32), ("src_plane_stride", ctypes.c_int64),
+                ("src_row_stride", ctypes.c_int64), ("dst_plane_stride", ctypes.c_int64),
+                ("dst_row_stride", ctypes.c_int64)]
 
 
 class Batch(ctypes.Structure):
@@ -128,6 +130,31 @@ def _geometry(x: torch.Tensor):
     H, W = x.shape[-2], x.shape[-1]
     planes = x.numel() // (H * W) if H * W else 0
     return planes, H, W
+
+
+def _strided_geometry(x: torch.Tensor):
+    """(planes, H, W, plane stride, row stride) of a (..., H, W) tensor whose
+    rows are contiguous and whose leading dimensions collapse into one plane
+    index with a uniform stride (crops and other views of larger tensors);
+    strides in elements, 0 where a single plane or row makes them moot."""
+    if x.dim() < 2:
+        raise ValueError("expected (..., H, W)")
+    H, W = x.shape[-2], x.shape[-1]
+    st = x.stride()
+    if W > 1 and st[-1] != 1:
+        raise ValueError("expected rows with unit stride along W")
+    ld = st[-2] if H > 1 else 0
+    planes = x.numel() // (H * W) if H * W else 0
+    ps = 0
+    lead = [(n, s) for n, s in zip(x.shape[:-2], st[:-2]) if n != 1]
+    if planes > 1:
+        ps = lead[-1][1]
+        expect = ps
+        for n, s in reversed(lead):
+            if s != expect:
+                raise ValueError("leading dimensions must collapse into one plane index with a uniform stride")
+            expect = s * n
+    return planes, H, W, ps, ld
 
 
 def forward_workspace_size(planes, H, W, dtype, r, T) -> int:
@@ -263,7 +290,8 @@ def _images(xs, outs, radii, iters):
     """The osbf_image list of a batch.  Every image and output must share the
     first image's dtype and device (the C ABI carries one dtype for the whole
     batch), each output must match its input's shape, and there must be one
-    radius and one iteration count per image."""
+    radius and one iteration count per image.  Images and outputs may be
+    strided views (rows contiguous): their strides go into the image list."""
     xs, outs, radii, iters = list(xs), list(outs), list(radii), list(iters)
     if not (len(xs) == len(outs) == len(radii) == len(iters)):
         raise ValueError(f"batch lists differ in length: {len(xs)} images, {len(outs)} outputs, "
@@ -279,8 +307,9 @@ def _images(xs, outs, radii, iters):
                 raise ValueError(f"image {i}: output shape {tuple(y.shape)} != input shape {tuple(x.shape)}")
     arr = (Image * len(xs))()
     for i, (x, y, r, T) in enumerate(zip(xs, outs, radii, iters)):
-        planes, H, W = _geometry(x)
-        arr[i] = Image(x.data_ptr(), y.data_ptr(), planes, H, W, int(r), int(T))
+        planes, H, W, sps, sld = _strided_geometry(x)
+        _, _, _, dps, dld = _strided_geometry(y)
+        arr[i] = Image(x.data_ptr(), y.data_ptr(), planes, H, W, int(r), int(T), sps, sld, dps, dld)
     return arr
 
 
@@ -293,7 +322,8 @@ class BatchPlan:
         if not xs:
             raise ValueError("empty batch")
         self.xs = list(xs)
-        self.outs = [torch.empty_like(x) for x in xs] if outs is None else list(outs)
+        self.outs = [torch.empty(x.shape, dtype=x.dtype, device=x.device) for x in xs] if outs is None \
+            else list(outs)
         dt = DTYPES[xs[0].dtype]
         self.images = _images(self.xs, self.outs, radii, iters)
         n = lib().osbf_batched_workspace_size(self.images, len(xs), dt)
@@ -313,7 +343,7 @@ class BatchPlan:
 def batched(xs, radii, iters, outs=None):
     """Filter a list of (..., H, W) device tensors of one dtype, each with its
     own radius and iteration count, in one batched call."""
-    outs = [torch.empty_like(x) for x in xs] if outs is None else list(outs)
+    outs = [torch.empty(x.shape, dtype=x.dtype, device=x.device) for x in xs] if outs is None else list(outs)
     dt = DTYPES[xs[0].dtype]
     imgs = _images(xs, outs, radii, iters)
     n = lib().osbf_batched_workspace_size(imgs, len(xs), dt)
@@ -399,7 +429,7 @@ def batched_autotune(xs, radii, iters) -> dict:
     """Tune the rows per batched work item for the radii of this batch
     (osbf_batched_autotune); returns {radius: rows}.  The batch's outputs are
     scratch during tuning."""
-    outs = [torch.empty_like(x) for x in xs]
+    outs = [torch.empty(x.shape, dtype=x.dtype, device=x.device) for x in xs]
     dt = DTYPES[xs[0].dtype]
     imgs = _images(xs, outs, radii, iters)
     n = lib().osbf_batched_autotune_workspace_size(imgs, len(xs), dt)

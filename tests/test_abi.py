@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.osbf_abi_version() == 1
+    assert lib.osbf_abi_version() == 2
     for s in range(6):
         assert lib.osbf_status_string(s)
     assert lib.osbf_status_string(99) == b"unknown status"
@@ -97,14 +97,15 @@ def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "osbf.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(osbf_image), sizeof(osbf_batch),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(osbf_image), sizeof(osbf_batch),'
         ' offsetof(osbf_batch, max_items), offsetof(osbf_batch, ws), offsetof(osbf_batch, identity),'
-        ' offsetof(osbf_image, radius));return 0;}\n')
+        ' offsetof(osbf_image, radius), offsetof(osbf_image, dst_row_stride));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(osbf.Image), ctypes.sizeof(osbf.Batch), osbf.Batch.max_items.offset,
-            osbf.Batch.ws.offset, osbf.Batch.identity.offset, osbf.Image.radius.offset]
+            osbf.Batch.ws.offset, osbf.Batch.identity.offset, osbf.Image.radius.offset,
+            osbf.Image.dst_row_stride.offset]
     assert got == want
 
 
@@ -121,6 +122,19 @@ def test_batched_rejects_bad_lists(lib):
     assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 1          # empty plane
     imgs[0].height = 8
     assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 3          # workspace missing
+    # strides: rows at least a row long, planes at least height rows apart
+    imgs[0].planes = 2
+    for field, value in (("src_row_stride", 7), ("dst_row_stride", -8), ("src_plane_stride", 63),
+                         ("dst_plane_stride", -1)):
+        setattr(imgs[0], field, value)
+        assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 1, field
+        setattr(imgs[0], field, 0)
+    imgs[0].src_row_stride, imgs[0].src_plane_stride = 10, 80
+    imgs[0].dst_row_stride, imgs[0].dst_plane_stride = 8, 64
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 3          # valid strides: workspace missing
+    imgs[0].src_row_stride = 1 << 28                                    # rows beyond 32-bit offsets
+    imgs[0].src_plane_stride = 0
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 2
 
 
 def test_volume_entry_validation(lib):

@@ -37,3 +37,23 @@ def test_batch_rejects_mixed_dtypes_shapes_and_lengths():
         osbf.batched([a, a], [1], [2, 2])
     with pytest.raises(ValueError, match="length"):
         osbf.BatchPlan([a, a], [1, 1], [2])
+
+
+def test_strided_geometry_of_views():
+    """Batch images may be views: rows must have unit stride and the leading
+    dimensions must collapse into one plane index with a uniform stride."""
+    big = torch.zeros(2, 4, 40, 50)
+    assert osbf._strided_geometry(big) == (8, 40, 50, 2000, 50)
+    assert osbf._strided_geometry(big[:, :, 3:30, 7:44]) == (8, 27, 37, 2000, 50)
+    assert osbf._strided_geometry(big[1, 2, 5:9, :]) == (1, 4, 50, 0, 50)
+    assert osbf._strided_geometry(big[0, 0, 5:6, 3:9]) == (1, 1, 6, 0, 0)
+    with pytest.raises(ValueError, match="collapse"):
+        osbf._strided_geometry(big[:, 1:3])              # channel slice: planes not uniformly spaced
+    with pytest.raises(ValueError, match="unit stride"):
+        osbf._strided_geometry(big.transpose(-1, -2))    # columns strided
+    # a batch of such views is marshalled with each side's strides
+    x = big[:, :, 3:30, 7:44]
+    y = torch.zeros(2, 4, 27, 37)
+    img = osbf._images([x], [y], [2], [3])[0]
+    assert (img.planes, img.height, img.width) == (8, 27, 37)
+    assert (img.src_plane_stride, img.src_row_stride, img.dst_plane_stride, img.dst_row_stride) == (2000, 50, 999, 37)

@@ -55,6 +55,53 @@ def test_batched_radius_classes(dev, radii):
         assert torch.equal(y, osbf.forward(x, r, T)), (tuple(x.shape), r, T)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_batched_strided_views(dev, dtype):
+    """Images and outputs given as views of larger tensors (crops, and
+    leading dimensions that collapse into one plane index) are read and
+    written in place through their strides: each output equals the
+    per-image forward of a contiguous copy bit for bit, and no element of
+    the larger output tensors outside the views is touched.  T = 1 writes
+    the strided output straight from the strided input; identity images
+    (r = 0 or T = 0) take the strided copy."""
+    rng = np.random.default_rng(41)
+    cases = [((1, 70, 90), (slice(None), slice(3, 60), slice(5, 84)), 2, 1),
+             ((3, 50, 64), (slice(None), slice(1, 49), slice(0, 63)), 1, 4),
+             ((2, 2, 40, 41), (slice(None), slice(None), slice(2, 39), slice(1, 40)), 3, 3),
+             ((1, 130, 300), (slice(None), slice(0, 129), slice(17, 275)), 5, 2),
+             ((1, 33, 33), (slice(None), slice(4, 30), slice(4, 30)), 8, 5),
+             ((2, 20, 30), (slice(None), slice(0, 20), slice(3, 30)), 0, 4),
+             ((1, 40, 40), (slice(None), slice(5, 35), slice(2, 33)), 4, 0)]
+    xs, outs, bigs, rs, ts = [], [], [], [], []
+    for k, (shape, crop, r, T) in enumerate(cases):
+        big = torch.from_numpy(synth.voronoi(shape[-2], shape[-1], 6, 0.05, rng,
+                                             C=int(np.prod(shape[:-2])))).reshape(shape)
+        x = big.to(dev).to(dtype)[crop]
+        if k % 2:   # every other output a view of a larger tensor too
+            ob = torch.full([d + 6 for d in x.shape[:-2]] + [x.shape[-2] + 7, x.shape[-1] + 9], -7.0,
+                            dtype=dtype, device=dev)
+            y = ob[tuple(slice(1, 1 + d) for d in x.shape[:-2]) + (slice(2, 2 + x.shape[-2]),
+                                                                    slice(3, 3 + x.shape[-1]))]
+        else:
+            ob, y = None, torch.empty(x.shape, dtype=dtype, device=dev)
+        assert k % 2 == 0 or not y.is_contiguous()
+        xs.append(x), outs.append(y), bigs.append(ob), rs.append(r), ts.append(T)
+    got = osbf.batched(xs, rs, ts, outs=outs)
+    for x, y, ob, r, T in zip(xs, got, bigs, rs, ts):
+        assert torch.equal(y, osbf.forward(x.contiguous(), r, T)), (tuple(x.shape), r, T)
+        if ob is not None:
+            mask = torch.ones_like(ob, dtype=torch.bool)
+            mask[tuple(slice(1, 1 + d) for d in x.shape[:-2]) + (slice(2, 2 + x.shape[-2]),
+                                                                 slice(3, 3 + x.shape[-1]))] = False
+            assert bool((ob[mask] == -7.0).all()), "write outside the output view"
+    # the prepared-batch path (no identity images) replays the same bits
+    keep = [i for i, (r, T) in enumerate(zip(rs, ts)) if r and T]
+    plan = osbf.BatchPlan([xs[i] for i in keep], [rs[i] for i in keep], [ts[i] for i in keep])
+    plan.launch()
+    for i, y in zip(keep, plan.outs):
+        assert torch.equal(y, got[i])
+
+
 def test_batched_small_images_against_oracle(dev):
     xs, rs, ts = _mixed_batch(dev, torch.float32, 2, n=10)
     outs = osbf.batched(xs, rs, ts)
