@@ -228,9 +228,14 @@ size_t osbf_batched_workspace_size(const osbf_image *imgs, int32_t n, osbf_dtype
 
 /*
  * osbf_batched_prepare -- plan a batch of T_j sweeps of Alg. 2 on each image
- * (all images of one dtype, radii in {0,1,2,3,4,5,8,10,16}) and upload its
- * tables into `ws` on `stream`.  `imgs` is host memory, read during the call.
+ * (all images of one dtype, radii 0..OSBF_MAX_RADIUS) and upload its tables
+ * into `ws` on `stream`.  `imgs` is host memory, read during the call.
  * Fills `batch`.  Not capturable into a graph (it copies from host memory).
+ * The batched kernels are compiled for r in {1,2,3,4,5,8,10,16}; images of
+ * another radius (contiguous planes only, else OSBF_ERROR_UNSUPPORTED) and
+ * identity images (r = 0 or T = 0) are left to osbf_batched, which runs
+ * them through osbf_forward's launches and copies; osbf_batched_launch
+ * refuses a batch that holds any (OSBF_ERROR_UNSUPPORTED).
  */
 osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype dtype,
                                  osbf_boundary boundary, void *ws, size_t ws_bytes,
@@ -247,7 +252,8 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
  */
 osbf_status osbf_batched_launch(const osbf_batch *batch, void *stream);
 
-/* Prepare and launch in one call. */
+/* Prepare and launch in one call; also runs the images the batched kernels
+ * do not take (see osbf_batched_prepare), each in its own workspace slice. */
 osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype,
                          osbf_boundary boundary, void *ws, size_t ws_bytes, void *stream);
 

@@ -801,6 +801,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct BatchImagePlan {
     int rounds = 0;
     int tw = 0, th = 0;  // strip width, rows per work item
+    size_t side_ws = 0;  // radius without a batched kernel: osbf_forward's workspace
 };
 
 // Per-image plans of a batch (row-streaming work items, one sweep per round)
@@ -812,6 +813,7 @@ struct BatchLayout {
     size_t descs_off = 0, items_off = 0, counts_off = 0, bufs_off = 0, total = 0;
     std::vector<size_t> buf_off;
     int identity = 0;
+    int side = 0;  // images of a radius without a batched kernel (osbf_forward's launches)
 };
 
 // Rows per work item: long enough that the r halo rows a chunk recomputes
@@ -900,8 +902,23 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
             L->identity++;
             continue;
         }
-        if (!fixed_radius(m.radius))
-            return fail(OSBF_ERROR_UNSUPPORTED, "image %d: batched radius %d not in {1,2,3,4,5,8,10,16}", j, m.radius);
+        if (!fixed_radius(m.radius)) {
+            // no batched kernel for this radius: osbf_batched runs the image
+            // through osbf_forward's own launches, on contiguous planes only
+            auto dense = [&](int64_t ld, int64_t ps) {
+                const int64_t l = ld ? ld : m.width;
+                return (l == m.width || m.height == 1) &&
+                       (m.planes == 1 || !ps || ps == (int64_t)m.height * m.width);
+            };
+            if (!dense(m.src_row_stride, m.src_plane_stride) || !dense(m.dst_row_stride, m.dst_plane_stride))
+                return fail(OSBF_ERROR_UNSUPPORTED,
+                            "image %d: radius %d has no batched kernel; its single-image path needs contiguous "
+                            "planes", j, m.radius);
+            b.side_ws = osbf_forward_workspace_size(m.planes, m.height, m.width, dtype, m.radius, m.iterations);
+            if (b.side_ws == (size_t)-1) return fail(OSBF_ERROR_INVALID_VALUE, "image %d: bad size", j);
+            L->side++;
+            continue;
+        }
         const int r = m.radius, step = stream_step(r);
         b.tw = ((batched_lanes() - 2 * r) / r) * r;
         b.th = (std::min(m.height, batch_rows(r, (int)dtype, rows_override)) + step - 1) / step * step;
@@ -932,6 +949,8 @@ osbf_status batch_layout(const osbf_image *imgs, int n, osbf_dtype dtype, BatchL
         L->buf_off[j] = off;
         if (L->img[j].rounds >= 2)
             off = align256(off + (size_t)imgs[j].planes * imgs[j].height * imgs[j].width * elem_bytes(dtype));
+        else if (L->img[j].side_ws)
+            off = align256(off + L->img[j].side_ws);
     }
     L->total = off;
     return OSBF_SUCCESS;
@@ -1065,6 +1084,7 @@ static osbf_status batched_prepare_impl(const osbf_image *imgs, int32_t n, osbf_
     batch->items_off = L.items_off;
     batch->counts_off = L.counts_off;
     batch->identity = L.identity;
+    batch->reserved[2] = L.side;                // images left to osbf_forward's launches (osbf_batched)
     batch->reserved[0] = any_big ? L.maxr : 0;  // class of the radius > 2 launches (0: none)
     batch->reserved[1] = any_small ? (int)std::max<int64_t>(8, (gs + 7) / 8 * 8) : 0;  // grid of the radius <= 2 launches
     // identity images are copied at launch: remember them in the tables is
@@ -1083,6 +1103,8 @@ osbf_status osbf_batched_launch(const osbf_batch *batch, void *stream_) {
     if (!batch) return fail(OSBF_ERROR_INVALID_VALUE, "batch must be non-NULL");
     if (batch->identity)
         return fail(OSBF_ERROR_UNSUPPORTED, "batch has identity images (r = 0 or T = 0): use osbf_batched");
+    if (batch->reserved[2])
+        return fail(OSBF_ERROR_UNSUPPORTED, "batch has images of a radius without a batched kernel: use osbf_batched");
     hipStream_t stream = (hipStream_t)stream_;
     const FwdLaunch *descs = (const FwdLaunch *)((const char *)batch->ws + batch->descs_off);
     const uint2 *items = (const uint2 *)((const char *)batch->ws + batch->items_off);
@@ -1107,8 +1129,17 @@ osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype, os
     osbf_status st = osbf_batched_prepare(imgs, n, dtype, boundary, ws, ws_bytes, &b, stream_);
     if (st != OSBF_SUCCESS) return st;
     hipStream_t stream = (hipStream_t)stream_;
+    BatchLayout L;  // the workspace slices of the images left to osbf_forward
+    if (b.reserved[2] && (st = batch_layout(imgs, n, dtype, &L)) != OSBF_SUCCESS) return st;
     for (int j = 0; j < n; ++j) {
         const osbf_image &m = imgs[j];
+        if (m.radius > 0 && m.iterations > 0 && !fixed_radius(m.radius)) {
+            const size_t bytes = L.img[j].side_ws;
+            st = osbf_forward(m.src, m.dst, m.planes, m.height, m.width, dtype, m.radius, m.iterations, boundary,
+                              nullptr, nullptr, 0, bytes ? (char *)ws + L.buf_off[j] : nullptr, bytes, stream_);
+            if (st != OSBF_SUCCESS) return st;
+            continue;
+        }
         if (m.radius == 0 || m.iterations == 0) {
             const size_t es = elem_bytes(dtype), row = (size_t)m.width * es;
             const size_t sld = m.src_row_stride ? (size_t)m.src_row_stride * es : row;
@@ -1127,6 +1158,7 @@ osbf_status osbf_batched(const osbf_image *imgs, int32_t n, osbf_dtype dtype, os
         }
     }
     b.identity = 0;
+    b.reserved[2] = 0;
     return osbf_batched_launch(&b, stream_);
 }
 
@@ -1172,7 +1204,8 @@ osbf_status osbf_batched_autotune(const osbf_image *imgs, int32_t n, osbf_dtype 
         osbf_status st = batched_prepare_impl(imgs, n, dtype, OSBF_BOUNDARY_REPLICATE, ws, ws_bytes, &b, stream_,
                                               rows);
         if (st != OSBF_SUCCESS) return st;
-        b.identity = 0;  // identity images take no kernel time
+        b.identity = 0;     // identity images take no kernel time
+        b.reserved[2] = 0;  // nor do they count here the images left to osbf_forward
         double best = 1e300;
         for (int rep = 0; rep < 4; ++rep) {
             if ((e = hipEventRecord(e0, stream)) != hipSuccess) return hip_fail(e, "event");

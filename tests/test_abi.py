@@ -112,8 +112,13 @@ def test_struct_layouts_match_header(tmp_path):
 def test_batched_rejects_bad_lists(lib):
     from paper_2108_05021_amd import osbf
     fake = ctypes.c_void_p(0x1000)
-    imgs = (osbf.Image * 1)(osbf.Image(fake, ctypes.c_void_p(0x2000), 1, 8, 8, 6, 2))
-    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 2          # radius without kernel
+    imgs = (osbf.Image * 1)(osbf.Image(fake, ctypes.c_void_p(0x2000), 1, 8, 8, 33, 2))
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 1          # radius above the limit
+    imgs[0].radius = 6                                                  # no batched kernel: single-image path
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 3          # workspace missing
+    imgs[0].src_row_stride = 9
+    assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 2          # that path needs contiguous planes
+    imgs[0].src_row_stride = 0
     imgs[0].radius = 2
     imgs[0].dst = fake
     assert lib.osbf_batched(imgs, 1, 0, 0, None, 0, None) == 1          # in place

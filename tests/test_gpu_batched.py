@@ -138,6 +138,24 @@ def test_graph_capture_and_replay(dev):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_batched_any_radius(dev, dtype):
+    """Radii without a batched kernel (any r up to the forward's limit) run
+    through osbf_forward's own launches inside osbf_batched, beside the
+    batched rounds of the others: every output equals the per-image forward
+    bit for bit."""
+    rng = np.random.default_rng(77)
+    radii = [6, 2, 7, 12, 4, 20, 1, 32, 9]
+    xs, ts = [], []
+    for i, r in enumerate(radii):
+        C, H, W = int(rng.choice([1, 2])), int(rng.integers(20, 140)), int(rng.integers(20, 170))
+        xs.append(torch.from_numpy(synth.voronoi(H, W, 6, 0.05, rng, C=C)).to(dev).to(dtype))
+        ts.append(int(rng.integers(1, 6)))
+    outs = osbf.batched(xs, radii, ts)
+    for x, y, r, T in zip(xs, outs, radii, ts):
+        assert torch.equal(y, osbf.forward(x, r, T)), (tuple(x.shape), r, T)
+
+
 def test_identity_and_errors(dev):
     x = torch.rand(2, 40, 50, device=dev)
     z = torch.rand(1, 30, 20, device=dev)
@@ -145,7 +163,10 @@ def test_identity_and_errors(dev):
     assert torch.equal(outs[0], x) and torch.equal(outs[1], z)
     assert torch.equal(outs[2], osbf.forward(x, 3, 2))
     with pytest.raises(osbf.OsbfError) as ei:
-        osbf.batched([x], [6], [2])                     # radius without a batched kernel
+        osbf.batched([x[:, 1:, :]], [6], [2])           # no batched kernel, and a strided view
+    assert ei.value.status == 2
+    with pytest.raises(osbf.OsbfError) as ei:
+        osbf.BatchPlan([x], [6], [2]).launch()          # the prepared path runs batched kernels only
     assert ei.value.status == 2
     with pytest.raises(osbf.OsbfError) as ei:
         osbf.batched([x], [2], [2], outs=[x])           # in place is rejected
