@@ -709,10 +709,13 @@ def main():
     line["parity"] = None if rec is None else {
         "workload": "the timed workload; FP64 oracle on 32x32 crops (tests/parity_report.py)",
         "tolerance": "1e-5 abs on the selected window's mean; near-tie flips within "
-                     "tau = 2^-19 N (1 + max|U|) are counted",
+                     "tau = 2^-19 N (1 + max|U|) are counted; end to end, 1e-5 outside the "
+                     "dependency cones of the sweeps where the GPU's window had another mean",
         **{r: {"flips": v["teacher_forced"]["flips"], "flip_pixels_checked": v["teacher_forced"]["pixels"],
                "teacher_forced_max_err": v["teacher_forced"]["max_err"],
                "err_max": v["end_to_end"]["err_max"], "err_mean": v["end_to_end"]["err_mean"],
+               "err_max_outside_flip_cones": v["end_to_end"].get("err_max_outside_flip_cones"),
+               "flip_cone_fraction": v["end_to_end"].get("flip_cone_fraction"),
                "replay_outliers": v["replay"]["outliers"], "replay_max_dev": v["replay"]["max_dev"]}
            for r, v in rec["headline"].items()}}
     cc = copy_ceiling()

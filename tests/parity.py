@@ -148,6 +148,49 @@ def replay_check_planes(u0, u_gpu, sels, r, tol=1e-5, max_outliers=0):
     return tot_bad, worst, flips
 
 
+def untethered_errors(u0, u_gpu, sels, r: int):
+    """One plane (H, W) against the oracle's own, untethered T sweeps: the
+    absolute errors and the flip cones.  A seed is a pixel where the GPU
+    selected, at sweep t, a window whose mean on the oracle's iterate differs
+    (by more than 1e-7) from the oracle's choice (equal-mean windows, as in
+    flat regions, give the same value); its difference may spread by r
+    pixels (Chebyshev) per later sweep, so the cone of a seed at sweep t
+    reaches r (T - 1 - t) pixels.  Every pixel outside all cones read, at
+    every sweep, only values both runs computed with windows of the same
+    mean."""
+    from scipy.ndimage import maximum_filter
+    u = np.asarray(u0, np.float64)
+    s = np.asarray(sels)
+    T = s.shape[0]
+    cone = np.zeros(u.shape, bool)
+    for t in range(T):
+        nxt, so, _, means = oracle.sweep(u, r, return_means=True)
+        m_gpu = np.take_along_axis(means, s[t][..., None].astype(np.int64), 2)[..., 0]
+        seed = (s[t] != so) & (np.abs(m_gpu - nxt) > 1e-7)
+        if seed.any():
+            d = r * (T - 1 - t)
+            cone |= maximum_filter(seed, size=2 * d + 1, mode="constant", cval=False) if d else seed
+        u = nxt
+    return np.abs(np.asarray(u_gpu, np.float64) - u), cone
+
+
+def untethered_check(u0, u_gpu, sels, r: int, tol: float = 1e-5):
+    """untethered_errors over the plane axes (u0, u_gpu (..., H, W), sels
+    (T, ..., H, W)); every pixel outside the flip cones must agree within
+    ``tol``.  Returns (max error outside the cones, fraction of pixels inside
+    them, max error overall)."""
+    u0 = np.asarray(u0, np.float64)
+    H, W = u0.shape[-2:]
+    a = u0.reshape(-1, H, W)
+    b = np.asarray(u_gpu, np.float64).reshape(-1, H, W)
+    s = np.asarray(sels).reshape(np.shape(sels)[0], -1, H, W)
+    errs, cones = zip(*(untethered_errors(a[p], b[p], s[:, p], r) for p in range(a.shape[0])))
+    err, cone = np.stack(errs), np.stack(cones)
+    outside = float(err[~cone].max()) if (~cone).any() else 0.0
+    assert outside <= tol, f"untethered error {outside:.3e} outside the flip cones"
+    return outside, float(cone.mean()), float(err.max())
+
+
 def check_fast_sweep(u_in, u_out, r: int, tol: float = 1e-5):
     """Teacher-forced check of one sweep of the fast approximation (Alg. 3):
     the GPU value must be the oracle's value of a near-minimal candidate

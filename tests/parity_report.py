@@ -9,7 +9,10 @@ Headline workload (3x2048x2048 FP32, r in {2, 5, 10}, T = 30), per radius:
                   GPU's window| (parity.sweep_region)
   end_to_end      the T = 30 GPU output against the untethered oracle run on
                   each crop grown by r*T (exact at the crop): max and mean
-                  |GPU - oracle|
+                  |GPU - oracle|, and the max outside the dependency cones
+                  of the sweeps where the GPU chose a window of another mean
+                  (parity.untethered_errors) with the share of the crop
+                  those cones cover
   replay          the oracle replaying the GPU's 30 selection maps on those
                   grown crops (parity.replay_region): outliers must be 0
 Precision workload (1x8192x8192, r = 16, T = 20): max / mean |GPU - oracle| of
@@ -68,7 +71,8 @@ def headline(dev, log):
             cur = nxt
         y, sels = osbf.forward(x, r, T, return_sel=True)
         assert torch.equal(y, cur), "the T-sweep call differs from single-sweep calls"
-        e2e, rep = [], {"outliers": 0, "max_dev": 0.0, "flips": 0, "pixels": 0}
+        e2e, outside, in_cones = [], [], []
+        rep = {"outliers": 0, "max_dev": 0.0, "flips": 0, "pixels": 0}
         for (p, y0, x0) in CROPS:
             (ya, yb, xa, xb), cuts = parity.region_of(H, W, y0, x0, SIZE, r * T)
             u0 = x[p, ya:yb, xa:xb].cpu().numpy()
@@ -78,14 +82,25 @@ def headline(dev, log):
             rep["max_dev"] = max(rep["max_dev"], dmax)
             rep["flips"] += flips
             rep["pixels"] += px
-            want = oracle.forward(u0.astype(np.float64), r, T)
+            # the oracle's own run on the crop grown by r*T (exact at the
+            # crop), and the cones of the sweeps where the runs' windows had
+            # different means (seeds outside the grown crop's exact region
+            # never reach the crop)
+            err, cone = parity.untethered_errors(u0, ug, sels[:, p, ya:yb, xa:xb].cpu().numpy(), r)
             cy, cx = y0 - ya, x0 - xa
-            e2e.append(np.abs(ug[cy:cy + SIZE, cx:cx + SIZE].astype(np.float64) - want[cy:cy + SIZE, cx:cx + SIZE]))
+            e_c, k_c = err[cy:cy + SIZE, cx:cx + SIZE], cone[cy:cy + SIZE, cx:cx + SIZE]
+            e2e.append(e_c)
+            outside.append(e_c[~k_c])
+            in_cones.append(k_c)
         e = np.concatenate([v.ravel() for v in e2e])
+        eo = np.concatenate(outside)
+        kc = np.concatenate([v.ravel() for v in in_cones])
         out[str(r)] = {
             "teacher_forced": {"sweeps": T, "crops": len(CROPS), **tf},
             "end_to_end": {"err_max": float(e.max()), "err_mean": float(e.mean()), "pixels": int(e.size),
-                           "margin": r * T},
+                           "margin": r * T,
+                           "err_max_outside_flip_cones": float(eo.max()) if eo.size else 0.0,
+                           "flip_cone_fraction": float(kc.mean())},
             "replay": rep,
         }
         log(f"headline r={r}: {out[str(r)]} ({time.time() - t0:.1f} s)")

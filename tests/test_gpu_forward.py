@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from paper_2108_05021_amd import osbf, synth
-from tests.parity import check_sweep_planes, crop_check, replay_check_planes, tau
+from tests.parity import check_sweep_planes, crop_check, replay_check_planes, tau, untethered_check
 
 pytestmark = pytest.mark.gpu
 
@@ -73,10 +73,10 @@ def test_teacher_forced_single_workload(dev):
     # end to end in the default plan: the oracle replays the GPU's selections
     got, sels = osbf.forward(_gpu(img, dev), 2, 10, return_sel=True)
     replay_check_planes(img, got.cpu().numpy(), sels.cpu().numpy(), 2, max_outliers=0)
-    # untethered: near-tie flips spread, so only the bulk must agree
-    want = oracle.forward(img.astype(np.float64), 2, 10)
-    err = np.abs(got.cpu().numpy() - want)
-    assert np.median(err) < 1e-6 and (err > 1e-5).mean() < 0.05
+    # untethered: exact outside the cones of the sweeps where the two runs
+    # chose different windows (near-tie flips spread r pixels per sweep)
+    _, in_cones, _ = untethered_check(img, got.cpu().numpy(), sels.cpu().numpy(), 2)
+    assert in_cones < 0.05
 
 
 @pytest.mark.parametrize("r", [1, 2, 4, 8, 16])

@@ -54,3 +54,32 @@ def test_sweep_region_matches_and_catches():
     wrong[20, 20] += 1e-3
     with pytest.raises(AssertionError):
         parity.sweep_region(u[reg], wrong[reg], sel[reg], r, (True,) * 4)
+
+
+def test_untethered_check_cones():
+    """untethered_check: the oracle's own run passes with no cone; a run that
+    took another window at one pixel and sweep (a planted flip, carried on
+    through the fixed-selection map) passes with the difference confined to
+    that pixel's cone; an error planted outside every cone is caught."""
+    rng = np.random.default_rng(80)
+    r, T = 2, 4
+    u0 = synth.voronoi(40, 46, 6, 0.05, rng)[0].astype(np.float64)
+    out, sel = oracle.forward(u0, r, T, return_sel=True)
+    outside, frac, _ = parity.untethered_check(u0, out, sel, r)
+    assert outside == 0.0 and frac == 0.0
+    # plant a flip at sweep 1, pixel (20, 23): a different window there, the
+    # oracle's own choices elsewhere and later (recomputed on the new iterate)
+    u = oracle.forward(u0, r, 1)
+    s1 = oracle.sweep(u, r)[1].copy()
+    s1[20, 23] = (s1[20, 23] + 3) % 8
+    u = oracle.apply_fixed(u, s1, r)
+    u, rest = oracle.forward(u, r, T - 2, return_sel=True)
+    sels = np.concatenate([sel[:1, 0], s1[None], rest[:, 0]])
+    outside, frac, worst = parity.untethered_check(u0, u, sels, r)
+    assert worst > 1e-5                     # the flip changed values ...
+    side = 2 * r * (T - 2) + 1              # ... only inside its cone
+    assert frac <= side * side / u0.size + 1e-12
+    bad = u.copy()
+    bad[2, 2] += 1e-3                       # far from (20, 23)
+    with pytest.raises(AssertionError, match="outside the flip cones"):
+        parity.untethered_check(u0, bad, sels, r)
