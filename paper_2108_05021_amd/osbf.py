@@ -144,6 +144,8 @@ def _strided_geometry(x: torch.Tensor):
     if W > 1 and st[-1] != 1:
         raise ValueError("expected rows with unit stride along W")
     ld = st[-2] if H > 1 else 0
+    if H > 1 and ld < W:
+        raise ValueError(f"rows overlap (row stride {ld} < width {W})")
     planes = x.numel() // (H * W) if H * W else 0
     ps = 0
     lead = [(n, s) for n, s in zip(x.shape[:-2], st[:-2]) if n != 1]
@@ -154,6 +156,8 @@ def _strided_geometry(x: torch.Tensor):
             if s != expect:
                 raise ValueError("leading dimensions must collapse into one plane index with a uniform stride")
             expect = s * n
+        if ps < H * max(ld, W):
+            raise ValueError(f"planes overlap (plane stride {ps} < height x row stride)")
     return planes, H, W, ps, ld
 
 

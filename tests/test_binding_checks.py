@@ -51,6 +51,10 @@ def test_strided_geometry_of_views():
         osbf._strided_geometry(big[:, 1:3])              # channel slice: planes not uniformly spaced
     with pytest.raises(ValueError, match="unit stride"):
         osbf._strided_geometry(big.transpose(-1, -2))    # columns strided
+    with pytest.raises(ValueError, match="rows overlap"):
+        osbf._strided_geometry(torch.zeros(1, 50).expand(40, 50))          # one row seen 40 times
+    with pytest.raises(ValueError, match="planes overlap"):
+        osbf._strided_geometry(torch.zeros(1, 40, 50).expand(3, 40, 50))  # one plane seen 3 times
     # a batch of such views is marshalled with each side's strides
     x = big[:, :, 3:30, 7:44]
     y = torch.zeros(2, 4, 27, 37)
