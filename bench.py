@@ -150,14 +150,14 @@ def _counter_rows(path):
         {k: len(v) for k, v in disp.items()}
 
 
-def write_counter_records(path):
+def write_counter_records(path, out_dir=None):
     """Write profiles/fwd_traffic.json and profiles/fwd_valu.json from the
     rocprofv3 counter runs of the timed step under `path` (subdirectories
     fetch, write: FETCH_SIZE / WRITE_SIZE of `bench.py --steps 1 --warmup 1
     --no-cpu-baseline --no-forms`; copy_fetch, copy_write: the same of
     `bench.py --copy-calibration`; sq: SQ_INSTS_VALU of the step).  The
     records carry the forward sources' hash and the plans, so bench.py uses
-    them only while both still hold."""
+    them only while both still hold.  `out_dir` defaults to profiles/."""
     import re
 
     import torch
@@ -216,7 +216,7 @@ def write_counter_records(path):
         "command": cmd.format(c="SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
                                 "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR", d="sq", p=step)}
     for name, rec in (("fwd_traffic.json", traffic), ("fwd_valu.json", valu_rec)):
-        with open(os.path.join(ROOT, "profiles", name), "w") as f:
+        with open(os.path.join(out_dir or os.path.join(ROOT, "profiles"), name), "w") as f:
             json.dump(rec, f, indent=1)
             f.write("\n")
     print(json.dumps({"traffic": per, "valu": valu_rec["lane_ops_per_px_sweep"]}))
