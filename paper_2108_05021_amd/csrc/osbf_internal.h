@@ -41,7 +41,7 @@ hipError_t launch_forward(int dtype, const FwdLaunch &a, hipStream_t s);
 // strips of tw columns, chunks of th
 // rows (th = 0: the launch chooses th so that the chunks fill the device's
 // resident workgroup slots once).
-int stream_step(int r);                       // rows per step (th is a multiple)
+int stream_step(int r);                       // th is a multiple (whole steps, whole blocks)
 bool stream_width_ok(int W, int es, int r, int rows);  // 32-bit row offsets suffice
 size_t stream2_lds_bytes(int RW, int r);      // the fused two-sweep kernel (k = 2)
 bool stream_fusable(int RW, int r);           // whether that kernel exists for (RW, r)

@@ -5,10 +5,10 @@
 namespace osbf {
 
 // P, V and H staging (CH blocks of three rows, block stride 3 (RW + 1) + 30)
-// and the Q ring (CH + r rows of RW + 1).
+// and the Q ring (the register ring's rows, of RW + 1).
 size_t stream_lds_bytes(int RW, int r) {
     const int ch = stream_step_rows(r);
-    return ((size_t)ch * (3 * (RW + 1) + 30) + (size_t)(ch + r) * (RW + 1)) * sizeof(float);
+    return ((size_t)ch * (3 * (RW + 1) + 30) + (size_t)stream_ring_rows(r, ch) * (RW + 1)) * sizeof(float);
 }
 
 // The fused two-sweep kernel: staging of both sweeps' P, their shared V and
@@ -21,7 +21,7 @@ size_t stream2_lds_bytes(int RW, int r) {
 
 bool stream_fusable(int RW, int r) { return stream2_radius(r) && RW >= 5 * r; }
 
-int stream_step(int r) { return stream_step_rows(r); }
+int stream_step(int r) { return stream_row_quantum(r); }
 
 // Whether a work item of `rows` rows (and its halo) of a plane W elements of
 // `es` bytes wide stays within the kernels' 32-bit row offsets.

@@ -30,12 +30,30 @@
 
 namespace osbf {
 
-// Rows per step for each compiled radius: whole blocks of r rows.  One block
-// is fastest (the LDS ring, and with it the workgroups per CU, is smallest),
-// except at r <= 2 where the two barriers per step dominate (MI355X,
-// 3x2048x2048 FP32).
+// Rows per step for each compiled radius: whole blocks of r rows, or a
+// whole fraction of one.  One block is fastest from r = 3 to 10 (the LDS
+// ring, and with it the workgroups per CU, is smallest), two at r <= 2 where
+// the two barriers per step dominate (MI355X, 3x2048x2048 FP32); half a
+// block at r = 16, whose LDS then fits three workgroups per CU instead of
+// two (1x8192x8192: 5% faster).
 constexpr int stream_step_rows(int r) {
-    return r == 1 ? 2 : r == 2 ? 4 : r;
+    return r == 1 ? 2 : r == 2 ? 4 : r == 16 ? 8 : r;
+}
+
+// Register (and Q) ring rows for r and CH rows per step.  Steps of whole
+// blocks keep the rows [s - r, s + CH); steps of part of a block also keep
+// row s - r - 1 (a block's later steps continue its running column sums,
+// which drop that row), rounded up to whole blocks so that the ring's period
+// in steps is a whole number of blocks.
+constexpr int stream_ring_rows(int r, int ch) {
+    return ch >= r ? r + ch : (r + 1 + ch + r - 1) / r * r;
+}
+
+constexpr int stream_gcd(int a, int b) { return b == 0 ? a : stream_gcd(b, a % b); }
+
+// Rows per work item are a multiple of this (whole steps and whole blocks).
+constexpr int stream_row_quantum(int r) {
+    return stream_step_rows(r) > r ? stream_step_rows(r) : r;
 }
 
 // Rows [row0, row1) of one plane that a work item touches, as buffer
@@ -76,27 +94,31 @@ __device__ __forceinline__ ItemRows item_rows(const FwdLaunch &a, int plane, int
 // [chunk * th, chunk * th + th) of one strip of one plane (shared by the
 // single-image and the batched kernels).
 //
-// Registers: the lane's P and V rows [s - R, s + CH) sit in two rings of
-// L = R + CH registers whose origin advances by CH rows per step, so the step
-// body is unrolled over the ring period NRB = CH / R + 1 and every ring slot,
-// every slot of the Q ring in LDS and every LDS offset is a compile-time
-// constant.  The next step's rows are loaded straight into the ring slots of
-// the rows [s - R, s - R + CH) once those are staged in LDS (the evaluation
-// reads c from LDS).  Lanes outside the image hold the clamped column, so the
+// Registers: the lane's P and V rows [s - R, s + CH) (from s - R - 1 when a
+// step is part of a block) sit in two rings of L registers whose origin
+// advances by CH rows per step, so the step body is unrolled over the ring
+// period NRB and every ring slot, every slot of the Q ring in LDS and every
+// LDS offset is a compile-time constant.  The next step's rows are loaded
+// straight into ring slots of rows no longer needed once the step's rows are
+// staged in LDS (the evaluation reads c from LDS).  Lanes outside the image hold the clamped column, so the
 // row sums read the replicate extension without clamping indices.
 template <int DT, int R, int RW, int CH, bool SEL, int MODE>
 __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float *lds) {
     using S = Storage<DT>;
     using T = typename S::T;
-    static_assert(CH % R == 0, "a step is whole blocks of R rows");
+    static_assert(CH % R == 0 || R % CH == 0, "a step is whole blocks of R rows or a whole part of one");
     static_assert(RW % 64 == 0 && RW >= 2 * R + R, "region width");
-    constexpr int M = CH / R;        // blocks per step
-    constexpr int NRB = M + 1;       // ring period in steps; Q ring of NRB * R = L rows
-    constexpr int L = R + CH;        // register ring length
+    constexpr int M = CH >= R ? CH / R : 1;     // blocks per step (at least one row-sum item per lane)
+    constexpr int MB = CH >= R ? 1 : R / CH;    // steps per block
+    constexpr int RB = CH >= R ? R : CH;        // rows of one block within a step
+    constexpr int OFF = MB == 1 ? R : R + 1;    // ring rows above the step's first new row
+    constexpr int L = stream_ring_rows(R, CH);  // register ring length, also the Q ring's
+    constexpr int NRB = L / stream_gcd(L, CH);  // ring period in steps (a multiple of MB)
+    static_assert(L >= OFF + CH && NRB % MB == 0, "ring");
     constexpr int PITCH = RW + 1;
     // staging, CH blocks of three rows: P of the i-th row evaluated this step
     // (row s - R + i), V of the step's i-th new row (row s + i), H of the
-    // i-th evaluated row; then the ring of Q (L rows).  Block stride = 1 mod
+    // i-th evaluated row; then the ring of Q (L rows, R + CH of them in use).  Block stride = 1 mod
     // 32 banks, as the ring's pitch, so that the row-sum items (consecutive
     // lanes = consecutive rows of one block of columns) hit distinct banks.
     constexpr int RS = 3 * PITCH + 30;
@@ -117,14 +139,15 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
     const int nsteps = (yend - Y0 + CH - 1) / CH;
 
     // rows up to the last one loaded or stored
-    const ItemRows io = item_rows<T>(a, plane, max(0, Y0 - R), min(H, Y0 + nsteps * CH), SEL);
+    const ItemRows io = item_rows<T>(a, plane, max(0, Y0 - OFF), min(H, Y0 + nsteps * CH), SEL);
     const int vld = clampi(x, 0, W - 1) * (int)sizeof(T);  // this lane's column (clamped)
     const int vst = x * (int)sizeof(T);
 
-    // This lane's row-sum work items, the same in every step: items of one
-    // block of R rows are consecutive, row fastest, so 32 consecutive lanes
-    // read 32 distinct banks (row pitch = 1 mod 32, column blocks R apart)
-    // when R divides 32.  CH * nb <= M * RW, so a lane has at most M items.
+    // This lane's row-sum work items, the same in every step: items of the
+    // step's rows of one block of R rows are consecutive, row fastest, so 32
+    // consecutive lanes read 32 distinct banks (row pitch = 1 mod 32, column
+    // blocks R apart) when R divides 32.  CH * nb <= M * RW, so a lane has at
+    // most M items.
     // ib: the item's first LDS column in its row, relative to the row start.
     const int nb = (xend - xa + R - 1) / R;
     int it_row[M], it_ib[M];
@@ -132,10 +155,10 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int it = lx + k * RW;
-        const int m = it / (R * nb), rem = it - m * (R * nb);
-        const int b = rem / R;
+        const int m = it / (RB * nb), rem = it - m * (RB * nb);
+        const int b = rem / RB;
         it_ok[k] = it < CH * nb;
-        it_row[k] = m * R + (rem - b * R);
+        it_row[k] = m * RB + (rem - b * RB);
         const int x0 = xa + b * R;
         it_ib[k] = x0 - R - ox;
         it_full[k] = x0 + R <= xend;
@@ -148,12 +171,12 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
 
     float PR[L], VR[L];  // physical rings
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        PR[j] = S::from_raw(S::load_raw(io.src, vld, io.ld_off(Y0 - R + j)));
+    for (int j = 0; j < OFF; ++j) {
+        PR[j] = S::from_raw(S::load_raw(io.src, vld, io.ld_off(Y0 - OFF + j)));
         VR[j] = 0.f;  // rows above Y0: never evaluated
     }
 #pragma unroll
-    for (int j = 0; j < CH; ++j) PR[R + j] = S::load_raw(io.src, vld, io.ld_off(Y0 + j));
+    for (int j = 0; j < CH; ++j) PR[OFF + j] = S::load_raw(io.src, vld, io.ld_off(Y0 + j));
 
     float out_v[CH];
     int out_i[CH];
@@ -181,42 +204,63 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
 
     auto step = [&](auto ph, int n) {
         constexpr int PH = decltype(ph)::value;
-        // physical slot of logical ring row j (row s - R + j)
+        // physical slot of logical ring row j (row s - OFF + j)
         auto sl = [](int j) { return (j + PH * CH) % L; };
         // Q ring row of image row s + j, j in [-R, CH)
         auto qrow = [](int j) { return (PH * CH + R + j) % L; };
         const int s = Y0 + n * CH;
-        // V of rows [s, s + CH) from P rows [s - R, s + CH), in registers
+        // V of rows [s, s + CH) from P rows [s - R - 1, s + CH), in registers:
+        // at a block's first row a direct sum of R + 1 rows, then slides
 #pragma unroll
-        for (int j = R; j < L; ++j) PR[sl(j)] = S::from_raw(PR[sl(j)]);
+        for (int j = OFF; j < OFF + CH; ++j) PR[sl(j)] = S::from_raw(PR[sl(j)]);
+        if constexpr (MB == 1) {
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            float v = PR[sl(m * R)];
+            for (int m = 0; m < M; ++m) {
+                float v = PR[sl(m * R)];
 #pragma unroll
-            for (int tt = 1; tt <= R; ++tt) v += PR[sl(m * R + tt)];
-            VR[sl(R + m * R)] = v;
+                for (int tt = 1; tt <= R; ++tt) v += PR[sl(m * R + tt)];
+                VR[sl(R + m * R)] = v;
 #pragma unroll
-            for (int tt = 1; tt < R; ++tt) {
-                v += PR[sl(R + m * R + tt)] - PR[sl(m * R + tt - 1)];
-                VR[sl(R + m * R + tt)] = v;
+                for (int tt = 1; tt < R; ++tt) {
+                    v += PR[sl(R + m * R + tt)] - PR[sl(m * R + tt - 1)];
+                    VR[sl(R + m * R + tt)] = v;
+                }
+            }
+        } else {
+            float v;
+            int t0 = 0;
+            if constexpr (PH % MB == 0) {  // the step starts a block
+                v = PR[sl(OFF - R)];
+#pragma unroll
+                for (int tt = 1; tt <= R; ++tt) v += PR[sl(OFF - R + tt)];
+                VR[sl(OFF)] = v;
+                t0 = 1;
+            } else {
+                v = VR[sl(OFF - 1)];  // the block's running sum at row s - 1
+            }
+#pragma unroll
+            for (int tt = t0; tt < CH; ++tt) {
+                v += PR[sl(OFF + tt)] - PR[sl(OFF + tt - R - 1)];
+                VR[sl(OFF + tt)] = v;
             }
         }
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            Sg[i * RS + lx] = PR[sl(i)];  // rows [s - R, s - R + CH), evaluated this step
-            Sg[i * RS + PITCH + lx] = VR[sl(R + i)];
+            Sg[i * RS + lx] = PR[sl(OFF - R + i)];  // rows [s - R, s - R + CH), evaluated this step
+            Sg[i * RS + PITCH + lx] = VR[sl(OFF + i)];
         }
         // the previous step's results, then the next step's loads into the
-        // slots of the rows just staged
+        // slots of rows no longer needed (for whole-block steps, the rows just
+        // staged)
         if (pending && own) store_step();
         if (n + 1 < nsteps) {
             if (s + 2 * CH <= H) {  // uniform: no clamped row, offsets step by a row
                 int o = io.ld_off(s + CH);
 #pragma unroll
-                for (int i = 0; i < CH; ++i, o += io.srow) PR[sl(i)] = S::load_raw(io.src, vld, o);
+                for (int i = 0; i < CH; ++i, o += io.srow) PR[sl(OFF + CH + i)] = S::load_raw(io.src, vld, o);
             } else {
 #pragma unroll
-                for (int i = 0; i < CH; ++i) PR[sl(i)] = S::load_raw(io.src, vld, io.ld_off(s + CH + i));
+                for (int i = 0; i < CH; ++i) PR[sl(OFF + CH + i)] = S::load_raw(io.src, vld, io.ld_off(s + CH + i));
             }
         }
         __syncthreads();
@@ -238,7 +282,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
                 }
                 int qo;
                 if constexpr (M == 1) {
-                    qo = qrow(0) * PITCH + it_ib[k] + R;  // i < R: no wrap
+                    qo = qrow(0) * PITCH + it_ib[k] + R;  // qrow(0) a multiple of CH, i < CH: no wrap
                     qo += i * PITCH;
                 } else {
                     const int qr = (PH * CH + R) % L + i;
@@ -290,7 +334,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
                 constexpr int ou = qrow(i - R) * PITCH, od = qrow(i) * PITCH, op = i * RS, oh = op + 2 * PITCH;
                 const float c = Sg[op + lx];
                 const float nw = Qr[ou + lx], ne = Qr[ou + lx + R], sw = Qr[od + lx], se = Qr[od + lx + R];
-                const float vu = VR[sl(i)], vd = VR[sl(i + R)];
+                const float vu = VR[sl(OFF - R + i)], vd = VR[sl(OFF + i)];
                 if constexpr (MODE == MODE_BOX) {
                     out_v[i] = S::bits(box_sum(nw, ne, sw, se, Sg[oh + lx], Sg[oh + lx + R], vu, vd, c) * inv_box);
                     out_i[i] = 0;
@@ -689,9 +733,10 @@ hipError_t launch_stream(const FwdLaunch &a, hipStream_t stream) {
         }
         const long long strips = (long long)a.tiles_x * a.planes;
         const int per_strip = (int)std::max<long long>(1, n / strips);
+        constexpr int RQ = stream_row_quantum(R);
         int rows = (a.H + per_strip - 1) / per_strip;
-        rows = std::max(CH, (rows + CH - 1) / CH * CH);
-        while (rows > CH && !fits(rows)) rows = std::max(CH, rows / 2 / CH * CH);
+        rows = std::max(RQ, (rows + RQ - 1) / RQ * RQ);
+        while (rows > RQ && !fits(rows)) rows = std::max(RQ, rows / 2 / RQ * RQ);
         if (!fits(rows)) return hipErrorInvalidValue;
         b.th = rows;
         b.tiles_y = (a.H + rows - 1) / rows;
