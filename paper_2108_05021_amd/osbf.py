@@ -53,7 +53,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2108_05021_amd.build")
     L = ctypes.CDLL(LIB_PATH)
     vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
     L.osbf_abi_version.argtypes = []

@@ -25,7 +25,7 @@ def _declared():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("libosbf.so is not built (run __graft_entry__.build())")
+        pytest.fail("libosbf.so is not built (run python -m paper_2108_05021_amd.build)")
     from paper_2108_05021_amd import osbf
     return osbf.lib()
 
