@@ -320,7 +320,11 @@ def form_batched(reps):
     rs = [it["r"] for it in items]
     ts = [it["T"] for it in items]
     pxit = sum(x.numel() * T for x, T in zip(xs, ts))
-    plan = osbf.BatchPlan(xs, rs, ts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = osbf.BatchPlan(xs, rs, ts)   # workspace, host planning and table upload, timed apart
+    torch.cuda.synchronize()
+    prepare_s = time.perf_counter() - t0
     plan.launch()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -355,6 +359,7 @@ def form_batched(reps):
     return {"workload": "256 images, H,W in [64,1024], C in {1,3}, Voronoi K=16 + N(0,0.05^2), "
                         "r in {1,2,4,8}, T in [5,30], f32",
             "mpix_it": round(pxit / 1e6, 1), "rounds": plan.batch.rounds, "grid": plan.batch.grid,
+            "prepare_ms": round(prepare_s * 1e3, 2),
             "graph_ms": round(t_graph * 1e3, 3), "mpix_it_s": round(pxit / t_graph / 1e6, 1),
             "eager_launch_mpix_it_s": round(pxit / t_eager / 1e6, 1),
             "plain_fp32_forward_per_image_mpix_it_s": round(pxit / t_single / 1e6, 1),
