@@ -14,6 +14,8 @@ plain FP32 forward on the same workload:
   bf16/f16  1x8192x8192 stored as BF16 / FP16, r=16, T=20, with the max/mean
             error against the FP64 oracle on crops (storage-only and total)
             from the committed parity record (tests/parity_report.py)
+  dram      1x8192x8192 FP32, r in {2,5,10}, T=10: the bench radii on an image
+            whose 2 x 256 MiB ping-pong does not fit the 256 MiB Infinity Cache
   fwd_bwd   32x3x512x512, r=3, T=10, loss sum(W*U): forward with uint8
             selection maps + backward, and with a checkpoint every 5 sweeps
   variants  the bench workload through the fast approximation (Alg. 3) and
@@ -300,11 +302,17 @@ def cpu_baseline(img, budget_s: float = 10.0):
                                              "mpix_it_s": round(small.size * 10 / t_small / 1e6, 2)}}
 
 
-def _timed(fn, reps, warmup=2):
+def _timed(fn, reps, warmup=2, warm_s=0.05):
+    """Seconds per call of fn over `reps` calls, after at least `warmup` calls
+    and `warm_s` seconds of untimed calls (the device's first tens of
+    milliseconds of work run measurably slower)."""
     import torch
-    for _ in range(warmup):
+    t_end = time.perf_counter() + warm_s
+    n = 0
+    while n < warmup or time.perf_counter() < t_end:
         fn()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        n += 1
     t0 = time.perf_counter()
     for _ in range(reps):
         fn()
@@ -398,6 +406,25 @@ def form_precision(reps, errors=True):
             for name in ("bf16", "f16"):
                 out[name].update(p[name])
             out["err_sample"] = p["crops"]
+    return out
+
+
+def form_dram(reps):
+    """The bench radii on an image whose ping-pong (2 x 256 MiB) is larger than
+    the 256 MiB Infinity Cache, so every sweep reads and writes DRAM (the
+    bench image's 2 x 48 MiB stay in that cache)."""
+    import torch
+    from paper_2108_05021_amd import osbf, synth
+    T = 10
+    x = torch.from_numpy(synth.workload_precision()[0]).cuda()[None]
+    pxit = x.numel() * T
+    out = {"workload": "1x8192x8192 Voronoi K=256 + N(0,0.02^2), FP32, r in {2,5,10}, T=10 "
+                       "(2 x 256 MiB ping-pong)"}
+    for r in RADII:
+        t = _timed(lambda: osbf.forward(x, r, T), reps)
+        gbs = 8 * pxit / t / 1e9
+        out[f"r{r}"] = {"mpix_it_s": round(pxit / t / 1e6, 1), "us_per_sweep": round(t / T * 1e6, 2),
+                        "achieved_GBs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
     return out
 
 
@@ -577,7 +604,7 @@ def form_variants(reps):
             "paper_context": "fast/exact ~0.6 and exact/box ~8 (MATLAB) or ~6 (C++) on a laptop CPU, r unstated"}
 
 
-FORMS = ("batched", "precision", "fwd_bwd", "variants", "volume", "gaussian", "small", "autotune")
+FORMS = ("batched", "precision", "dram", "fwd_bwd", "variants", "volume", "gaussian", "small", "autotune")
 
 
 def run_form(name, args, reps=5):
@@ -590,7 +617,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched/bf16/f16/fwd+bwd forms")
     ap.add_argument("--no-errors", action="store_true", help="skip the oracle error crops of the bf16/f16 form")

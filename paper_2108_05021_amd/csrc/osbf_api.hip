@@ -1,5 +1,6 @@
 // C ABI of the one-sided box filter: argument validation, launch planning and
 // the sweep driver.  All device work is enqueued on the caller's stream.
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -155,6 +156,25 @@ const TunedShape kTunedSmall[] = {{1, GEOM_64x48, 6, 0}, {2, GEOM_64x60, 5, 0}, 
                                   {4, GEOM_64x60, 2, 0}, {5, GEOM_64x60, 2, 0}, {8, GEOM_64x60, 1, 0},
                                   {10, GEOM_64x60, 1, 0}, {16, GEOM_128x64, 1, 0}};
 
+// From 2^25 plane-pixels up the FP32 ping-pong (8 B per pixel) no longer fits
+// the 256 MiB Infinity Cache, so every sweep reads and writes DRAM.  Two fused
+// sweeps per launch (half the DRAM bytes per sweep) then pay from r = 1 to 4,
+// wider strips with 64-row chunks at r = 5 and narrow strips at r = 16.
+// Measured on MI355X, 1x8192^2 and 3x4096^2, FP32, T=10, the same plan sweep
+// as the large-image table, best of two passes in opposite orders (us per
+// sweep, 1x8192^2 then 3x4096^2, against that table's plan): r=1 91.0 / 71.0
+// (96.1 / 72.3), r=2 101.0 / 78.5 (128.3 / 93.1), r=3 102.8 / 78.5 (127.0 /
+// 95.4), r=4 111.7 / 87.3 (135.9 / 100.9), r=5 118.4 / 92.0 (159.9 / 113.9),
+// r=16 178.1 / 140.9 (186.0 / 147.3); r=8 and 10 keep their plans.
+const TunedShape kTunedHuge[] = {{1, GEOM_S128, 2, 64}, {1, GEOM_64x48, 3, 0},
+                                 {2, GEOM_S192, 2, 64}, {2, GEOM_64x48, 2, 0},
+                                 {3, GEOM_S192, 2, 0}, {3, GEOM_64x48, 2, 0},
+                                 {4, GEOM_S192, 2, 0}, {4, GEOM_64x48, 1, 0},
+                                 {5, GEOM_S256, 1, 64}, {5, GEOM_64x60, 1, 0},
+                                 {8, GEOM_S192, 1, 0}, {8, GEOM_64x48, 1, 0},
+                                 {10, GEOM_S192, 1, 0}, {10, GEOM_64x60, 1, 0},
+                                 {16, GEOM_S128, 1, 0}, {16, GEOM_128x64, 1, 0}};
+
 // Autotune cache: (device model, radius, dtype, size class) -> plan measured
 // by osbf_autotune, and (device model, dtype, radius) -> rows per batched
 // work item measured by osbf_batched_autotune.  Guarded by a mutex; every
@@ -224,7 +244,7 @@ void tune_file_read_locked() {
         int r, dt, cls, geom, rw, rh, k, th, rows;
         if (sscanf(line, "fwd %255s %d %d %d %d %d %d %d %d", model, &r, &dt, &cls, &geom, &rw, &rh, &k, &th) == 9) {
             const Plan p = plan_from_fields(geom, rw, rh, k, th, r);
-            if (p.tw && valid_dtype(dt) && cls >= 0 && cls <= 2)
+            if (p.tw && valid_dtype(dt) && cls >= 0 && cls <= 3)
                 g_tune[std::make_tuple(std::string(model), r, dt, cls)] = p;
         } else if (sscanf(line, "batch %255s %d %d %d", model, &dt, &r, &rows) == 4) {
             if (valid_dtype(dt) && r >= 1 && r <= OSBF_MAX_RADIUS && rows >= 1 && rows <= 4096)
@@ -257,10 +277,10 @@ void tune_file_write_locked() {
     if (ok) rename(tmp.c_str(), path);
 }
 
-// 0: below 2^17 plane-pixels, 1: below 2^20, 2: larger.
+// 0: below 2^17 plane-pixels, 1: below 2^20, 2: below 2^25, 3: larger.
 int size_class(int planes, int H, int W) {
     const long long px = (long long)planes * H * W;
-    return px < (1LL << 17) ? 0 : px < (1LL << 20) ? 1 : 2;
+    return px < (1LL << 17) ? 0 : px < (1LL << 20) ? 1 : px < (1LL << 25) ? 2 : 3;
 }
 
 // Rows per workgroup of a plan (the streaming kernel rounds to whole steps;
@@ -320,7 +340,10 @@ Plan choose_plan_model(int planes, int H, int W, int r, int T) {
                 if (p.tw && p.lds_bytes() <= limit) return p;
             }
         }
-        for (const auto &t : kTuned) {
+        const TunedShape *tab = cls == 3 ? kTunedHuge : kTuned;
+        const size_t ntab = cls == 3 ? std::size(kTunedHuge) : std::size(kTuned);
+        for (size_t i = 0; i < ntab; ++i) {
+            const TunedShape &t = tab[i];
             if (t.r != r) continue;
             if (stream_geom(t.geom) && !stream_width_ok(W, 4, r, stream_step(r))) continue;
             Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
