@@ -285,7 +285,7 @@ osbf_status osbf_forward_plan(int32_t planes, int32_t height, int32_t width, osb
  * plan the measured tables would use is kept unless another is more than
  * 3% faster.  Blocks until done (do not call during stream capture).  The winner is
  * cached per (device, radius, dtype, size class: planes*height*width below
- * 2^17, below 2^20, below 2^25, or larger) and used by later osbf_forward / osbf_backward /
+ * 2^17, below 2^20, up to 2^25, or larger) and used by later osbf_forward / osbf_backward /
  * osbf_forward_plan calls of that class (batches keep their own work
  * items); OSBF_PLAN in the environment still takes precedence.
  * Every plan computes the same bits, so tuning changes speed, never

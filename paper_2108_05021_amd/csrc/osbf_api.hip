@@ -156,20 +156,33 @@ const TunedShape kTunedSmall[] = {{1, GEOM_64x48, 6, 0}, {2, GEOM_64x60, 5, 0}, 
                                   {4, GEOM_64x60, 2, 0}, {5, GEOM_64x60, 2, 0}, {8, GEOM_64x60, 1, 0},
                                   {10, GEOM_64x60, 1, 0}, {16, GEOM_128x64, 1, 0}};
 
-// From 2^25 plane-pixels up the FP32 ping-pong (8 B per pixel) no longer fits
-// the 256 MiB Infinity Cache, so every sweep reads and writes DRAM.  Two fused
+// Above 2^25 plane-pixels, two more tables.  While the ping-pong (two
+// iterates) is larger than the 256 MiB Infinity Cache (FP32, or 16-bit
+// storage above 2^26 pixels), every sweep reads and writes DRAM: two fused
 // sweeps per launch (half the DRAM bytes per sweep) then pay from r = 1 to 4,
-// wider strips with 64-row chunks at r = 5 and narrow strips at r = 16.
-// Measured on MI355X, 1x8192^2 and 3x4096^2, FP32, T=10, the same plan sweep
-// as the large-image table, best of two passes in opposite orders (us per
-// sweep, 1x8192^2 then 3x4096^2, against that table's plan): r=1 91.0 / 71.0
-// (96.1 / 72.3), r=2 101.0 / 78.5 (128.3 / 93.1), r=3 102.8 / 78.5 (127.0 /
-// 95.4), r=4 111.7 / 87.3 (135.9 / 100.9), r=5 118.4 / 92.0 (159.9 / 113.9),
-// r=16 178.1 / 140.9 (186.0 / 147.3); r=8 and 10 keep their plans.
-const TunedShape kTunedHuge[] = {{1, GEOM_S128, 2, 64}, {1, GEOM_64x48, 3, 0},
+// 256-lane strips with 64-row chunks at r = 5 and 128-lane strips at r = 16
+// (measured on 1x8192^2 and 3x4096^2, FP32, T=10, best of two passes in
+// opposite orders, us per sweep against the large-image table's plan: r=1
+// 91.0 / 71.0 (96.1 / 72.3), r=2 101.0 / 78.5 (128.3 / 93.1), r=3 102.8 /
+// 78.5 (127.0 / 95.4), r=4 111.7 / 87.3 (135.9 / 100.9), r=5 118.4 / 92.0
+// (159.9 / 113.9), r=16 178.1 / 140.9 (186.0 / 147.3); r=8 and 10 keep
+// theirs).  16-bit storage up to 2^26 pixels (a ping-pong within the cache)
+// takes one sweep per launch with 64-row chunks, which there beat both the
+// fused plans and the chunks that fill the device once (1x8192^2 BF16 and
+// FP16: r=2 87.3 against 93.0 and 103.0 us, r=4 92.7 against 112.7 and
+// 116.1, r=5 100.2 against 129.7).
+const TunedShape kTunedDram[] = {{1, GEOM_S128, 2, 64}, {1, GEOM_64x48, 3, 0},
                                  {2, GEOM_S192, 2, 64}, {2, GEOM_64x48, 2, 0},
                                  {3, GEOM_S192, 2, 0}, {3, GEOM_64x48, 2, 0},
                                  {4, GEOM_S192, 2, 0}, {4, GEOM_64x48, 1, 0},
+                                 {5, GEOM_S256, 1, 64}, {5, GEOM_64x60, 1, 0},
+                                 {8, GEOM_S192, 1, 0}, {8, GEOM_64x48, 1, 0},
+                                 {10, GEOM_S192, 1, 0}, {10, GEOM_64x60, 1, 0},
+                                 {16, GEOM_S128, 1, 0}, {16, GEOM_128x64, 1, 0}};
+const TunedShape kTunedHuge[] = {{1, GEOM_S128, 1, 0}, {1, GEOM_64x48, 3, 0},
+                                 {2, GEOM_S128, 1, 64}, {2, GEOM_64x48, 2, 0},
+                                 {3, GEOM_S128, 1, 64}, {3, GEOM_64x48, 2, 0},
+                                 {4, GEOM_S128, 1, 64}, {4, GEOM_64x48, 1, 0},
                                  {5, GEOM_S256, 1, 64}, {5, GEOM_64x60, 1, 0},
                                  {8, GEOM_S192, 1, 0}, {8, GEOM_64x48, 1, 0},
                                  {10, GEOM_S192, 1, 0}, {10, GEOM_64x60, 1, 0},
@@ -277,10 +290,10 @@ void tune_file_write_locked() {
     if (ok) rename(tmp.c_str(), path);
 }
 
-// 0: below 2^17 plane-pixels, 1: below 2^20, 2: below 2^25, 3: larger.
+// 0: below 2^17 plane-pixels, 1: below 2^20, 2: up to 2^25, 3: larger.
 int size_class(int planes, int H, int W) {
     const long long px = (long long)planes * H * W;
-    return px < (1LL << 17) ? 0 : px < (1LL << 20) ? 1 : px < (1LL << 25) ? 2 : 3;
+    return px < (1LL << 17) ? 0 : px < (1LL << 20) ? 1 : px <= (1LL << 25) ? 2 : 3;
 }
 
 // Rows per workgroup of a plan (the streaming kernel rounds to whole steps;
@@ -306,7 +319,7 @@ bool tuned_plan(int planes, int H, int W, int r, int T, int dtype, Plan *out) {
     return true;
 }
 
-Plan choose_plan_model(int planes, int H, int W, int r, int T);
+Plan choose_plan_model(int planes, int H, int W, int r, int T, int dtype);
 
 // The launch plan: OSBF_PLAN if set, else an autotuned plan for this device
 // and problem class, else the measured table of the problem's size class,
@@ -314,13 +327,13 @@ Plan choose_plan_model(int planes, int H, int W, int r, int T);
 Plan choose_plan(int planes, int H, int W, int r, int T, int dtype) {
     Plan p;
     if (!getenv("OSBF_PLAN") && tuned_plan(planes, H, W, r, T, dtype, &p)) return p;
-    return choose_plan_model(planes, H, W, r, T);
+    return choose_plan_model(planes, H, W, r, T, dtype);
 }
 
 // OSBF_PLAN="geom,k[,rows]" forces a plan (tests and tuning): geom 0 is the
 // generic kernel (region chosen by cost), 1.. the fixed and streaming
 // geometries (enum Geom); rows sets the streaming kernel's rows per workgroup.
-Plan choose_plan_model(int planes, int H, int W, int r, int T) {
+Plan choose_plan_model(int planes, int H, int W, int r, int T, int dtype) {
     const size_t limit = lds_limit();
     const int kmax = T > 0 ? std::min(T, 8) : 1;
     int force_geom = -1, force_k = -1, force_rows = 0;
@@ -340,8 +353,11 @@ Plan choose_plan_model(int planes, int H, int W, int r, int T) {
                 if (p.tw && p.lds_bytes() <= limit) return p;
             }
         }
-        const TunedShape *tab = cls == 3 ? kTunedHuge : kTuned;
-        const size_t ntab = cls == 3 ? std::size(kTunedHuge) : std::size(kTuned);
+        // above 2^25 pixels: DRAM-bound while the two iterates outgrow the
+        // 256 MiB Infinity Cache
+        const bool dram = (long long)planes * H * W * (long long)elem_bytes((osbf_dtype)dtype) * 2 > (256LL << 20);
+        const TunedShape *tab = cls < 3 ? kTuned : dram ? kTunedDram : kTunedHuge;
+        const size_t ntab = cls < 3 ? std::size(kTuned) : dram ? std::size(kTunedDram) : std::size(kTunedHuge);
         for (size_t i = 0; i < ntab; ++i) {
             const TunedShape &t = tab[i];
             if (t.r != r) continue;
@@ -1464,7 +1480,7 @@ osbf_status osbf_autotune(const void *src, void *dst, int32_t planes, int32_t H,
     // the plan osbf_forward would use without tuning (the measured tables)
     size_t incumbent = cands.size();
     if (!getenv("OSBF_PLAN")) {
-        const Plan t = choose_plan_model(planes, H, W, r, T);
+        const Plan t = choose_plan_model(planes, H, W, r, T, (int)dtype);
         for (size_t c = 0; c < cands.size() && incumbent == cands.size(); ++c)
             if (cands[c].geom == t.geom && cands[c].k == t.k && cands[c].tw == t.tw &&
                 plan_rows(cands[c], r) == plan_rows(t, r))

@@ -2,7 +2,7 @@
 device): images below 2^17 and below 2^20 plane-pixels take the two
 small-image tables (the tiled kernel with several fused sweeps per launch),
 larger ones the row-streaming plans (two fused sweeps per launch at r = 1,
-one above), and from 2^25 plane-pixels the huge-image table; fused sweeps never exceed T and the launch count covers T.  Every
+one above), and above 2^25 plane-pixels the two huge-image tables; fused sweeps never exceed T and the launch count covers T.  Every
 plan gives the same bits (the GPU tests check that); this pins which one the
 tables pick."""
 import pytest
@@ -40,26 +40,38 @@ def test_large_images_use_streaming_plans(shape, r):
         assert p["launches"] == -(-T // p["fused"])
 
 
-# From 2^25 plane-pixels (FP32 ping-pong beyond the 256 MiB Infinity Cache):
-# (strip width, fused sweeps, rows per workgroup) of the huge-image table.
-HUGE = {1: (128, 2, 64), 2: (192, 2, 64), 3: (192, 2, 0), 4: (192, 2, 0), 5: (256, 1, 64),
+# Above 2^25 plane-pixels: (strip width, fused sweeps, rows per workgroup)
+# of the table for a ping-pong larger than the 256 MiB Infinity Cache (FP32;
+# 16-bit above 2^26 pixels) and of the one for 16-bit storage within it.
+DRAM = {1: (128, 2, 64), 2: (192, 2, 64), 3: (192, 2, 0), 4: (192, 2, 0), 5: (256, 1, 64),
         8: (192, 1, 0), 10: (192, 1, 0), 16: (128, 1, 0)}
+HUGE16 = {1: (128, 1, 0), 2: (128, 1, 64), 3: (128, 1, 64), 4: (128, 1, 64), 5: (256, 1, 64),
+          8: (192, 1, 0), 10: (192, 1, 0), 16: (128, 1, 0)}
+CASES = [((1, 8192, 8192), torch.float32, DRAM), ((3, 4096, 4096), torch.float32, DRAM),
+         ((3, 8192, 8192), torch.bfloat16, DRAM), ((1, 8192, 8192), torch.bfloat16, HUGE16),
+         ((1, 8192, 8192), torch.float16, HUGE16), ((3, 4096, 4096), torch.float16, HUGE16)]
 
 
-@pytest.mark.parametrize("shape", [(1, 8192, 8192), (3, 4096, 4096), (2, 4096, 4096)])
-@pytest.mark.parametrize("r", sorted(HUGE))
-def test_huge_images_use_their_table(shape, r):
-    lanes, k, rows = HUGE[r]
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("r", sorted(DRAM))
+def test_huge_images_use_their_tables(case, r):
+    shape, dtype, table = CASES[case]
+    lanes, k, rows = table[r]
     step = {1: 2, 2: 4, 16: 8}.get(r, r)
     for T in (1, 2, 10):
-        p = osbf.forward_plan(*shape, torch.float32, r, T)
-        assert p["fused"] == min(k, T), (shape, r, T, p)
-        assert p["tile"][0] == (lanes - 2 * p["fused"] * r) // r * r, (shape, r, T, p)
-        assert p["tile"][1] == -(-rows // step) * step, (shape, r, T, p)
+        p = osbf.forward_plan(*shape, dtype, r, T)
+        assert p["fused"] == min(k, T), (shape, dtype, r, T, p)
+        assert p["tile"][0] == (lanes - 2 * p["fused"] * r) // r * r, (shape, dtype, r, T, p)
+        assert p["tile"][1] == -(-rows // step) * step, (shape, dtype, r, T, p)
         assert p["launches"] == -(-T // p["fused"])
-    # one pixel-row short of 2^25 plane-pixels: the large-image table
-    p = osbf.forward_plan(1, 4096, 8191, torch.float32, r, 10)
-    assert p["fused"] == (2 if r == 1 else 1) and p["tile"][1] == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("r", sorted(DRAM))
+def test_up_to_2_pow_25_pixels_is_a_large_image(dtype, r):
+    # exactly 2^25 plane-pixels (an FP32 ping-pong of 256 MiB): the large-image table
+    p = osbf.forward_plan(2, 4096, 4096, dtype, r, 10)
+    assert p["fused"] == (2 if r == 1 else 1) and p["tile"][1] == 0, (dtype, r, p)
 
 
 def test_plan_override_from_environment(monkeypatch):
