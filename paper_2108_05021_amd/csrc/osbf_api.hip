@@ -130,15 +130,29 @@ double plan_cost(const Plan &p, int H, int W, int r) {
 // r = 1, where the fused two-sweep kernel is 6-10% faster (20.4-21.1 against
 // 21.6-23.4 us per sweep; at r = 2 it is 5% slower, at r = 3 even); the
 // later entries are fallbacks for devices whose LDS does not fit the first.
+// At r = 4, 8 and 16 the 128-lane strips have the smallest worst-case ratio
+// to the fastest plan over 3x2048^2, 1x4096^2, 2x2000x3000, 8x1024^2 and
+// 1x1400^2 (T=10: 1.04, 1.03, 1.05 against 1.07, 1.07, 1.05 for 192-lane
+// strips, which are at most 1.3% faster on 3x2048^2).  At r = 2, 5 and 10
+// the plans are the fastest on 3x2048^2; on other shapes 192-lane strips at
+// r = 5 gain up to 10% and the fused 128-lane kernel at r = 2 up to 5%,
+// which the autotuner finds.
 struct TunedShape { int r, geom, k, rows; };
 const TunedShape kTuned[] = {{1, GEOM_S128, 2, 0}, {1, GEOM_64x48, 3, 0},
                              {2, GEOM_S192, 1, 0}, {2, GEOM_64x48, 2, 0},
                              {3, GEOM_S128, 1, 0}, {3, GEOM_64x48, 2, 0},
-                             {4, GEOM_S192, 1, 0}, {4, GEOM_64x48, 1, 0},
+                             {4, GEOM_S128, 1, 0}, {4, GEOM_64x48, 1, 0},
                              {5, GEOM_S128, 1, 0}, {5, GEOM_64x60, 1, 0},
-                             {8, GEOM_S192, 1, 0}, {8, GEOM_64x48, 1, 0},
+                             {8, GEOM_S128, 1, 0}, {8, GEOM_64x48, 1, 0},
                              {10, GEOM_S192, 1, 0}, {10, GEOM_64x60, 1, 0},
-                             {16, GEOM_S192, 1, 0}, {16, GEOM_128x64, 1, 0}};
+                             {16, GEOM_S128, 1, 0}, {16, GEOM_128x64, 1, 0}};
+
+// From 2^20 up to 2^21 plane-pixels at r = 1 and 2 the tiled kernel with
+// fused sweeps still beats the streaming plans (1x1024^2 / 1x1400^2, T=10,
+// us per sweep: r=1 4.43 / 6.70 against 5.43 / 7.02, r=2 4.99 / 7.68
+// against 7.25 / 9.01); from r = 3 up the streaming plans are within 1.19x
+// of the best there.
+const TunedShape kTunedMid[] = {{1, GEOM_64x60, 5, 0}, {2, GEOM_64x48, 2, 0}};
 
 // Images below 2^20 plane-pixels are launch- and latency-bound: a few short
 // launches of the tiled kernel with several fused sweeps beat the streaming
@@ -348,6 +362,13 @@ Plan choose_plan_model(int planes, int H, int W, int r, int T, int dtype) {
         const int cls = size_class(planes, H, W);
         if (cls < 2) {
             for (const auto &t : cls == 0 ? kTunedTiny : kTunedSmall) {
+                if (t.r != r) continue;
+                Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
+                if (p.tw && p.lds_bytes() <= limit) return p;
+            }
+        }
+        if (cls == 2 && (long long)planes * H * W < (1LL << 21)) {
+            for (const auto &t : kTunedMid) {
                 if (t.r != r) continue;
                 Plan p = make_plan(t.geom, kGeomDims[t.geom][0], kGeomDims[t.geom][1], r, std::min(t.k, kmax));
                 if (p.tw && p.lds_bytes() <= limit) return p;

@@ -1,8 +1,8 @@
 """Host-side checks of the launch-plan tables (osbf_forward_plan needs no
 device): images below 2^17 and below 2^20 plane-pixels take the two
 small-image tables (the tiled kernel with several fused sweeps per launch),
-larger ones the row-streaming plans (two fused sweeps per launch at r = 1,
-one above), and above 2^25 plane-pixels the two huge-image tables; fused sweeps never exceed T and the launch count covers T.  Every
+images up to 2^21 keep tiles at r = 1 and 2, larger ones take the
+row-streaming plans (two fused sweeps per launch at r = 1, one above), and above 2^25 plane-pixels the two huge-image tables; fused sweeps never exceed T and the launch count covers T.  Every
 plan gives the same bits (the GPU tests check that); this pins which one the
 tables pick."""
 import pytest
@@ -29,15 +29,37 @@ def test_small_images_use_tiled_plans(shape, r):
         assert p["tile"][0] % r == 0 and p["tile"][1] % r == 0
 
 
-@pytest.mark.parametrize("shape", [(1, 1024, 1024), (3, 2048, 2048), (1, 4096, 300)])
-@pytest.mark.parametrize("r", sorted(SMALL_K))
+# strip lanes of the large-image table (2^21 up to 2^25 plane-pixels)
+LARGE_LANES = {1: 128, 2: 192, 3: 128, 4: 128, 5: 128, 8: 128, 10: 192, 16: 128}
+
+
+@pytest.mark.parametrize("shape", [(1, 2048, 1024), (3, 2048, 2048), (1, 4096, 600), (2, 4096, 4096)])
+@pytest.mark.parametrize("r", sorted(LARGE_LANES))
 def test_large_images_use_streaming_plans(shape, r):
     for T in (1, 2, 30):
         p = osbf.forward_plan(*shape, torch.float32, r, T)
         assert p["tile"][1] == 0, (shape, r, T, p)  # streaming: rows chosen at launch
         # two fused sweeps per launch at r = 1 (never more than T), else one
         assert p["fused"] == (min(2, T) if r == 1 else 1), (shape, r, T, p)
+        assert p["tile"][0] == (LARGE_LANES[r] - 2 * p["fused"] * r) // r * r, (shape, r, T, p)
         assert p["launches"] == -(-T // p["fused"])
+
+
+@pytest.mark.parametrize("shape", [(1, 1024, 1024), (1, 1400, 1400), (1, 4096, 300)])
+@pytest.mark.parametrize("r", sorted(LARGE_LANES))
+def test_mid_images_keep_tiles_at_small_radii(shape, r):
+    # 2^20 up to 2^21 plane-pixels: the tiled kernel (64x60 with 5 fused
+    # sweeps at r = 1, 64x48 with 2 at r = 2), streaming plans from r = 3
+    for T in (1, 3, 10):
+        p = osbf.forward_plan(*shape, torch.float32, r, T)
+        if r == 1:
+            assert p["fused"] == min(5, T) and p["tile"][1] > 0, (shape, T, p)
+            assert p["tile"] == (64 - 2 * p["fused"], 60 - 2 * p["fused"]), (shape, T, p)
+        elif r == 2:
+            assert p["fused"] == min(2, T) and p["tile"][1] > 0, (shape, T, p)
+            assert p["tile"] == ((64 - 4 * p["fused"]) // 2 * 2, (48 - 4 * p["fused"]) // 2 * 2), (shape, T, p)
+        else:
+            assert p["tile"][1] == 0 and p["fused"] == 1, (shape, r, T, p)
 
 
 # Above 2^25 plane-pixels: (strip width, fused sweeps, rows per workgroup)
