@@ -468,15 +468,23 @@ hipError_t enqueue_forward(const Plan &plan, int k, const void *in, void *out, u
 // Adjoint kernel choice: the row-streaming kernel for its radii, then the
 // fixed-geometry tiled kernel, then the smallest square region of the generic
 // kernel that fits the device's LDS.  OSBF_ADJOINT=fixed or generic forces
-// the tiled kernels (tests compare all of them bit for bit).
+// the tiled kernels (tests compare all of them bit for bit);
+// OSBF_ADJOINT_ROWS sets the streaming kernel's rows per workgroup (rounded
+// up to whole blocks of r; tests and tuning).
 bool adjoint_tile(int r, int W, BwdLaunch *b) {
     const char *env = getenv("OSBF_ADJOINT");
     const bool force_generic = env && strcmp(env, "generic") == 0;
     const bool force_fixed = env && strcmp(env, "fixed") == 0;
     b->fixed = 0;
     size_t fixed_lds = 0;
+    const bool stream = !force_generic && !force_fixed && adjoint_stream_tile(r, &b->tw, &b->th, &fixed_lds);
+    if (stream) {
+        const char *rows = getenv("OSBF_ADJOINT_ROWS");
+        const int n = rows ? atoi(rows) : 0;
+        if (n > 0 && n <= 4096) b->th = (n + r - 1) / r * r;
+    }
     // (the streaming kernel addresses a chunk's rows through 32-bit offsets)
-    if (!force_generic && !force_fixed && adjoint_stream_tile(r, &b->tw, &b->th, &fixed_lds) &&
+    if (stream &&
         fixed_lds <= lds_limit() && (long long)(b->th + 6 * r) * W * 4 < (1LL << 31)) {
         b->fixed = 2;
         b->pitch = b->arr = 0;

@@ -58,6 +58,22 @@ def test_adjoint_kernels_agree(dev, monkeypatch, shape, r):
     assert torch.equal(stream, fixed)
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 5, 10, 16])
+def test_adjoint_independent_of_chunk_rows(dev, monkeypatch, r):
+    """Block anchors and fold order do not depend on where a workgroup's
+    chunk of rows starts, so the streaming adjoint gives the same bits for
+    any rows per workgroup (OSBF_ADJOINT_ROWS), over several sweeps."""
+    rng = np.random.default_rng(70 + r)
+    img = synth.voronoi(301, 257, 8, 0.05, rng, C=2)
+    T = 3
+    _, sel = osbf.forward(_gpu(img, dev), r, T, return_sel=True)
+    g = _gpu(rng.normal(size=img.shape), dev)
+    ref = osbf.backward(g, r, T, sel=sel)
+    for rows in (r, 12, 40, 97, 400):
+        monkeypatch.setenv("OSBF_ADJOINT_ROWS", str(rows))
+        assert torch.equal(osbf.backward(g, r, T, sel=sel), ref), rows
+
+
 def test_adjoint_full_size_properties(dev, monkeypatch):
     """32x3x512x512, r=3 (the fwd+bwd workload): one adjoint sweep conserves
     the gradient's sum, matches the tiled kernels bit for bit, and matches
