@@ -244,7 +244,7 @@ osbf_status osbf_batched_prepare(const osbf_image *imgs, int32_t n, osbf_dtype d
 /*
  * osbf_batched_launch -- run a prepared batch: per round (every unfinished
  * image advances by one sweep) one persistent launch for the images of
- * radius above 2 and one for those of radius 1 and 2 (a kernel compiled for
+ * radius above 4 and one for those of radius 1 to 4 (a kernel compiled for
  * those radii only, with fewer registers).  Only
  * kernel launches and device-to-device copies are enqueued, so the call can
  * be captured into a HIP graph and replayed; each replay recomputes dst from

@@ -890,8 +890,9 @@ struct BatchLayout {
 // MPix*it/s).
 constexpr int kBatchRows = 64;
 
-// Per round, two kernel classes (radius above 2, radius 1 and 2), each with
-// the offsets of its 8 XCD bins in the round's item list plus the end.
+// Per round, two kernel classes (radius above kBatchLeanMaxR, and up to it),
+// each with the offsets of its 8 XCD bins in the round's item list plus the
+// end.
 constexpr int kBinTable = 2 * 9;
 
 // Relative cost of one lane-row of a work item by radius (time per sweep of
@@ -1088,10 +1089,14 @@ static osbf_status batched_prepare_impl(const osbf_image *imgs, int32_t n, osbf_
             cur = out;
         }
     }
-    // a round's items per kernel class (radius above 2, radius 1 and 2),
-    // each split over the 8 XCD bins by cost
+    // a round's items per kernel class (radius above kBatchLeanMaxR, and up
+    // to it), each split over the 8 XCD bins by cost
     bool any_big = false, any_small = false;
-    for (int j : order) (imgs[j].radius > 2 ? any_big : any_small) = true;
+    int lean_maxr = 0;
+    for (int j : order) {
+        (imgs[j].radius > kBatchLeanMaxR ? any_big : any_small) = true;
+        if (imgs[j].radius <= kBatchLeanMaxR) lean_maxr = std::max(lean_maxr, (int)imgs[j].radius);
+    }
     std::vector<int> counts((size_t)kBinTable * std::max(L.rounds, 1), 0);
     for (int r = 0; r < L.rounds; ++r) {
         std::vector<uint2> list;
@@ -1099,14 +1104,14 @@ static osbf_status batched_prepare_impl(const osbf_image *imgs, int32_t n, osbf_
         for (int cls = 0; cls < 2; ++cls) {
             double total = 0;
             for (int j : order) {
-                if (r >= L.img[j].rounds || (imgs[j].radius > 2) != (cls == 0)) continue;
+                if (r >= L.img[j].rounds || (imgs[j].radius > kBatchLeanMaxR) != (cls == 0)) continue;
                 const FwdLaunch &a = descs[(size_t)r * n + j];
                 total += (double)a.tiles_x * a.tiles_y * a.planes * (a.th + a.r) * item_row_cost(a.r);
             }
             const double cap = std::max(total / (8.0 * 32.0), 1e-9);  // at least ~32 groups per bin
             std::vector<BinGroup> groups;
             for (int j : order) {
-                if (r >= L.img[j].rounds || (imgs[j].radius > 2) != (cls == 0)) continue;
+                if (r >= L.img[j].rounds || (imgs[j].radius > kBatchLeanMaxR) != (cls == 0)) continue;
                 const FwdLaunch &a = descs[(size_t)r * n + j];
                 const int cnt = a.tiles_x * a.tiles_y * a.planes;
                 const double ic = (a.th + a.r) * item_row_cost(a.r);
@@ -1136,7 +1141,7 @@ static osbf_status batched_prepare_impl(const osbf_image *imgs, int32_t n, osbf_
     int slots = 0, slots_small = 0;
     if (L.rounds && any_big && (e = batched_slots((int)dtype, L.maxr, &slots)) != hipSuccess)
         return hip_fail(e, "occupancy");
-    if (L.rounds && any_small && (e = batched_slots((int)dtype, 2, &slots_small)) != hipSuccess)
+    if (L.rounds && any_small && (e = batched_slots((int)dtype, lean_maxr, &slots_small)) != hipSuccess)
         return hip_fail(e, "occupancy");
     const int64_t g = std::min<int64_t>(L.max_items, std::max(slots, 1));
     const int64_t gs = std::min<int64_t>(L.max_items, std::max(slots_small, 1));
@@ -1153,8 +1158,9 @@ static osbf_status batched_prepare_impl(const osbf_image *imgs, int32_t n, osbf_
     batch->counts_off = L.counts_off;
     batch->identity = L.identity;
     batch->reserved[2] = L.side;                // images left to osbf_forward's launches (osbf_batched)
-    batch->reserved[0] = any_big ? L.maxr : 0;  // class of the radius > 2 launches (0: none)
-    batch->reserved[1] = any_small ? (int)std::max<int64_t>(8, (gs + 7) / 8 * 8) : 0;  // grid of the radius <= 2 launches
+    batch->reserved[0] = any_big ? L.maxr : 0;  // class of the launches above the lean radii (0: none)
+    batch->reserved[1] = any_small ? (int)std::max<int64_t>(8, (gs + 7) / 8 * 8) : 0;  // grid of the lean launches
+    batch->reserved[3] = any_small ? lean_maxr : 0;  // class of the lean launches
     // identity images are copied at launch: remember them in the tables is
     // not needed; the launch re-reads the host list through the caller.
     return OSBF_SUCCESS;
@@ -1182,10 +1188,10 @@ osbf_status osbf_batched_launch(const osbf_batch *batch, void *stream_) {
         const uint2 *it = items + (size_t)r * batch->max_items;
         hipError_t e = hipSuccess;
         const int *offs = counts + (size_t)kBinTable * r;
-        if (batch->reserved[0])  // radius above 2
+        if (batch->reserved[0])  // radius above kBatchLeanMaxR
             e = launch_batched_round(batch->dtype, batch->reserved[0], d, it, offs, batch->grid, stream);
-        if (e == hipSuccess && batch->reserved[1])  // radius 1 and 2, after the others in the list
-            e = launch_batched_round(batch->dtype, 2, d, it, offs + 9, batch->reserved[1], stream);
+        if (e == hipSuccess && batch->reserved[1])  // the lean radii, after the others in the list
+            e = launch_batched_round(batch->dtype, batch->reserved[3], d, it, offs + 9, batch->reserved[1], stream);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
     return OSBF_SUCCESS;

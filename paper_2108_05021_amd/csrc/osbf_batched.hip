@@ -13,10 +13,11 @@
 //
 // Every item runs the same code as the single-image streaming kernel; its
 // window sums are position-deterministic, so the batch gives the same bits as
-// filtering each image alone.  A kernel compiled for radii up to 2 needs far
+// filtering each image alone.  A kernel compiled for radii up to 4 needs far
 // fewer registers than one for radii up to 8 (or 16), so a round runs as two
-// launches: the items of radius above 2 (listed first) in the larger class,
-// then those of radius 1 and 2 in the small one.
+// launches: the items of radius above 4 (listed first) in the larger class,
+// then those of radius 1 to 4 in the lean one (the 256-image batch: 401 K
+// against 387 K MPix*it/s with the split at radius 2).
 #include "osbf_stream_device.h"
 
 namespace osbf {
@@ -92,10 +93,13 @@ static const void *batched_fn(int dtype) {
     }
 }
 
-// Kernel classes by the largest radius they run: 2 (71 VGPRs, 7 waves per
-// SIMD), 8 (122, 4 waves) and 16.
+// Kernel classes by the largest radius they run: 2 and 4 (about 70 VGPRs, 7
+// waves per SIMD), 8 (104, 4 waves) and 16.
 static const void *batched_function(int dtype, int maxr) {
-    return maxr <= 2 ? batched_fn<2>(dtype) : maxr <= 8 ? batched_fn<8>(dtype) : batched_fn<16>(dtype);
+    return maxr <= 2   ? batched_fn<2>(dtype)
+           : maxr <= 4 ? batched_fn<4>(dtype)
+           : maxr <= 8 ? batched_fn<8>(dtype)
+                       : batched_fn<16>(dtype);
 }
 
 // Resident workgroups of the round kernel on the current device.

@@ -72,9 +72,11 @@ bool adjoint_stream_tile(int r, int *tw, int *th, size_t *lds_bytes);
 bool adjoint_fixed_tile(int r, int *tw, int *th, size_t *lds_bytes);
 
 // Batched rounds (row-streaming work items, batched_lanes()-wide strips); maxr
-// is the largest radius the launch runs (selects the kernel class, 2, 8 or
-// 16, and its LDS); bins (device) holds the offsets of the launch's 8 XCD
-// bins in the round's item list and their end.
+// is the largest radius the launch runs (selects the kernel class, 2, 4, 8
+// or 16, and its LDS); bins (device) holds the offsets of the launch's 8 XCD
+// bins in the round's item list and their end.  Items of radius up to
+// kBatchLeanMaxR run in a launch of their own, in the lean classes.
+constexpr int kBatchLeanMaxR = 4;
 int batched_lanes();
 size_t batched_lds_bytes(int maxr);
 hipError_t batched_slots(int dtype, int maxr, int *slots);

@@ -37,9 +37,9 @@ def test_batched_equals_single(dev, dtype):
         assert torch.equal(y, osbf.forward(x, r, T)), (tuple(x.shape), r, T)
 
 
-@pytest.mark.parametrize("radii", [[1, 2], [2], [3, 4, 5, 8], [10, 16], [1, 16]])
+@pytest.mark.parametrize("radii", [[1, 2], [2], [3, 4], [3, 4, 5, 8], [4, 8], [10, 16], [1, 16], [2, 4, 5]])
 def test_batched_radius_classes(dev, radii):
-    """A round runs its items of radius above 2 and of radius 1 and 2 as two
+    """A round runs its items of radius above 4 and of radius 1 to 4 as two
     launches of different kernel classes: batches with only one class, with
     both, and with rounds where one class has finished, equal the per-image
     forward bit for bit."""
@@ -49,7 +49,7 @@ def test_batched_radius_classes(dev, radii):
         C, H, W = int(rng.choice([1, 3])), int(rng.integers(5, 200)), int(rng.integers(5, 300))
         xs.append(torch.from_numpy(synth.voronoi(H, W, 8, 0.05, rng, C=C)).to(dev))
         rs.append(radii[i % len(radii)])
-        ts.append(int(rng.integers(1, 9)) if rs[-1] > 2 else int(rng.integers(4, 12)))
+        ts.append(int(rng.integers(1, 9)) if rs[-1] > 4 else int(rng.integers(4, 12)))
     outs = osbf.batched(xs, rs, ts)
     for x, y, r, T in zip(xs, outs, rs, ts):
         assert torch.equal(y, osbf.forward(x, r, T)), (tuple(x.shape), r, T)
