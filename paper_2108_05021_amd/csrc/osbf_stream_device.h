@@ -209,6 +209,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
         // Q ring row of image row s + j, j in [-R, CH)
         auto qrow = [](int j) { return (PH * CH + R + j) % L; };
         const int s = Y0 + n * CH;
+        wave_priority<1>();
         // V of rows [s, s + CH) from P rows [s - R - 1, s + CH), in registers:
         // at a block's first row a direct sum of R + 1 rows, then slides
 #pragma unroll
@@ -264,6 +265,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
             }
         }
         __syncthreads();
+        wave_priority<2>();
 
         // Q of rows [s, s + CH) ∩ [Y0, yend) into the ring and H of the rows
         // evaluated this step, [s - R, s - R + CH), into Hr; columns [xa, xend).
@@ -325,6 +327,7 @@ __device__ __forceinline__ void fwd_stream_item(const FwdLaunch &a, int t, float
                 }
             }
         }
+        wave_priority<0>();
         __syncthreads();
 
         // selection and update of rows [s - R, s + CH - R) ∩ [Y0, yb)
