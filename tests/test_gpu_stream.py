@@ -166,3 +166,19 @@ def test_fused_full_size(dev):
         for geom in (5, 6, 7):
             with plan(geom, 2):
                 assert torch.equal(osbf.forward(x, r, 4), want), (r, geom)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_huge_image_tables_equal_other_plans(dev, dtype):
+    """Above 2^25 plane-pixels (1x6144x6144) the tables for DRAM-bound images
+    (FP32: two fused sweeps up to r = 4, 64-row chunks) and for 16-bit
+    storage within the cache (64-row chunks) give the bits of the
+    large-image plans and of the tiled kernel, over 3 sweeps (a fused launch
+    and a single one), with maps."""
+    x = torch.from_numpy(synth.workload_rgb(H=6144, W=6144)[:1].copy()).to(dev).to(dtype)
+    for r in (1, 2, 4, 5, 16):
+        y, s = osbf.forward(x, r, 3, return_sel=True)
+        for geom in (7, 1):
+            with plan(geom, 1):
+                y1, s1 = osbf.forward(x, r, 3, return_sel=True)
+            assert torch.equal(y, y1) and torch.equal(s, s1), (r, geom)
