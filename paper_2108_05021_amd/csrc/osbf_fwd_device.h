@@ -238,15 +238,18 @@ __device__ __forceinline__ void fwd_tile(const FwdLaunch &a, int tile_x, int til
         const int xa = max(0, X0 - e), xb = min(W, X0 + TW + e);
         const int ya = max(0, Y0 - e), yb = min(H, Y0 + TH + e);
 
+        wave_priority<1>();  // phases A and B gate the barriers; C fills in
         if (interior)
             phase_v<R, false>(Pi, Vi, pitch, r, H, xa - r, xb + r, ya, yb + r, tx, ty);
         else
             phase_v<R, true>(Pi, Vi, pitch, r, H, max(0, xa - r), min(W, xb + r), ya, yb + r, tx, ty);
         __syncthreads();
+        wave_priority<2>();
         if (interior)
             phase_qh<R, false, MODE>(Pi, Vi, Qi, Hi, pitch, r, W, xa, xb + r, ya, yb + r, yb, tx, ty);
         else
             phase_qh<R, true, MODE>(Pi, Vi, Qi, Hi, pitch, r, W, xa, xb + r, ya, yb + r, yb, tx, ty);
+        wave_priority<0>();
         __syncthreads();
 
         // Phase C: selection and update on [xa, xb) x [ya, yb).
@@ -513,6 +516,7 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
         const int xa = max(0, X0 - e), xb = min(W, X0 + TW + e);
         const int ya = max(0, Y0 - e), yb = min(H, Y0 + TH + e);
 
+        wave_priority<1>();  // phases A and B gate the barriers; C fills in (as the streaming kernel)
         if (j == 0)  // the load of the tile + halo, fused with the first phase A
             fixed_load_phase_v<DT, R, RW, RH, NT>(src, P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
         else if (interior)
@@ -520,10 +524,12 @@ __device__ __forceinline__ void fwd_fixed(const FwdLaunch &a, int tile_x, int ti
         else
             fixed_phase_v<R, RW, RH, NT, true>(P, V, lx, ly, ox, oy, H, W, xa, xb, ya, yb);
         __syncthreads();
+        wave_priority<2>();
         if (interior)
             fixed_phase_qh<R, RW, RH, NT, false, MODE>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
         else
             fixed_phase_qh<R, RW, RH, NT, true, MODE>(P, V, Q, Hs, lr, lb, ox, oy, W, xa, xb, ya, yb);
+        wave_priority<0>();
         __syncthreads();
 
         // Phase C: selection and update on [xa, xb) x [ya, yb).
