@@ -215,6 +215,10 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
             if (n >= nsl) return;  // uniform over the workgroup
             float *P = lds + (n & 1) * ARR;
             float *V = lds + (2 + (n & 1)) * ARR;
+            // the phases that end in barriers first, as in the planar kernels
+            // (256^3, T=10: r = 1, 2, 3 5%, 11%, 14% faster; the 1024-thread
+            // workgroups of r = 4 2% slower, so they keep one priority)
+            if constexpr (NT <= 512) wave_priority<1>();
             v_phase(P, V);
             if (out_pending) {
                 dst[out_at] = out_v;
@@ -223,10 +227,12 @@ __global__ __launch_bounds__(NT) void fwd3d_kernel(Fwd3dLaunch a) {
             }
             if (n + 1 < nsl) load_rows(z0 - R + n + 1);
             __syncthreads();
+            if constexpr (NT <= 512) wave_priority<2>();
             if (interior)
                 phase_qh_items<R, RW, NT, false>(P, V, Q, Hs, tid, ox, oy, W, xa, xb, ya, yb);
             else
                 phase_qh_items<R, RW, NT, true>(P, V, Q, Hs, tid, ox, oy, W, xa, xb, ya, yb);
+            if constexpr (NT <= 512) wave_priority<0>();
             __syncthreads();
             if (!own) return;
             planar_quantities<R, PITCH>(P, V, Q, Hs, (y - oy) * PITCH + lx, ring[s], cring[s]);
