@@ -652,6 +652,11 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
         auto sl = [](int j) { return (j + PH * CH) % L; };  // logical j <-> row s0 - R + j
         const int s0 = qy0 + n * CH;
         float *const VF = VF0 + (n & 1) * CH * PITCH;  // by step parity
+        // wave priorities by phase: the VALU-heavy vertical pass fills in (0)
+        // behind the horizontal pass between the barriers (2) and the fold
+        // and store (1); 32x3x512^2, r = 3: the adjoint 1.8% faster (the
+        // forward's order, vertical pass at 1, timed the same as none)
+        wave_priority<0>();
 #pragma unroll
         for (int j = 0; j < CH; ++j) convert(sl(2 * R + j), s0 + R + j);
         // vertical pass: the operations of adjoint_fixed_kernel's block, for
@@ -711,6 +716,7 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
             }
         }
         __syncthreads();
+        wave_priority<2>();
 
         // horizontal pass: Gpad = Hl[HL] + Hr[HR] - VF over VF
 #pragma unroll
@@ -741,6 +747,7 @@ __global__ __launch_bounds__(RW) void adjoint_stream_kernel(BwdLaunch a) {
                 }
             }
         }
+        wave_priority<1>();
         __syncthreads();
 
         // fold and store: q row qy belongs to output row clamp(qy); an output
