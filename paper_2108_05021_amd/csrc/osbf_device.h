@@ -157,9 +157,10 @@ __device__ __forceinline__ Pick select8(const float d[8]) {
 // staging, 2 for the row pass, 0 for the evaluation) shortened the forward
 // bench step by 1.6-2.4% and the batched rounds by 2% on MI355X; in the
 // tiled kernels (phases A and B before their barriers, C after) small images
-// ran 1-7% faster (the fused two-sweep, adjoint, box and Gaussian kernels
-// showed no gain).  Priorities change the order in which waves issue, never
-// what they compute.
+// ran 1-7% faster, in the volume filter 5-14%; the streaming adjoint gained
+// with another order (its VALU-heavy phase lowest), and the fused two-sweep,
+// box and Gaussian kernels showed no gain.  Priorities change the order in
+// which waves issue, never what they compute.
 template <int P>
 __device__ __forceinline__ void wave_priority() { __builtin_amdgcn_s_setprio(P); }
 
